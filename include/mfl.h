@@ -1,0 +1,174 @@
+/*
+ * mfl.h -- C ABI of the matrix-free high-order Laplace library for AMD MI355X (gfx950).
+ *
+ * Method: Kronbichler & Wall, "A performance comparison of continuous and
+ * discontinuous Galerkin methods with fast multigrid solvers" (arXiv 1611.03029).
+ *   - operator: -div(kappa grad u) on hexahedra, continuous Q_k (Sec. 2.1, eq.
+ *     poisson_fem) or symmetric interior penalty DG (Sec. 2.2, eq. poisson_dgsip with
+ *     the boundary extension of eq. bc_dgsip), evaluated matrix-free by sum
+ *     factorization with k+1 Gauss points per direction (Sec. 3, eq. mf_eval);
+ *   - solver: conjugate gradients preconditioned by one geometric multigrid V-cycle
+ *     with a Chebyshev-accelerated Jacobi smoother of degree 5 over
+ *     [0.06, 1.2] * lambda_max, lambda_max from 15 CG iterations, embedding transfer,
+ *     and a Chebyshev coarse solver with an a-priori error bound of 1e-3 (Sec. 4.1).
+ *   - additions: the V-cycle may run in FP32 inside the FP64 outer CG; an adjoint
+ *     solve and a per-cell gradient with respect to a cellwise kappa.
+ *
+ * Mesh: the unit cube [0,1]^3 with N_c^3 cells (lexicographic, x fastest), either
+ * Cartesian or deformed by x + a sin(pi x) sin(pi y) sin(pi z) (1,1,1) through the
+ * isoparametric Q_k map at the Gauss-Lobatto support points (Sec. 2).
+ *
+ * Vectors:
+ *   - CG: full-length (k N_c + 1)^3 vector, lexicographic on the grid of per-cell
+ *     Gauss-Lobatto positions, x fastest; boundary DoFs included.  With Dirichlet
+ *     conditions the operator is the identity on boundary DoFs and their columns
+ *     are eliminated (symmetric positive definite on the whole space).
+ *   - DG (SIPG): cell-major, N_c^3 (k+1)^3 values, local index i + n j + n^2 l
+ *     (n = k+1), basis = Lagrange polynomials in the Gauss-Legendre points.
+ *
+ * Conventions:
+ *   - every function returns MFL_OK (0) or a negative error code and never throws;
+ *     mfl_last_error() describes the last failure of the calling thread;
+ *   - all vector and field pointers are DEVICE pointers owned by the caller; the
+ *     library never allocates device memory: its device state lives in a caller
+ *     provided workspace (size from mfl_query), owned by the caller, which must
+ *     stay valid and unmodified until mfl_destroy;
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work
+ *     asynchronously on it, except where a function states that it synchronizes;
+ *   - one handle must not be used from two host threads at the same time.
+ */
+#ifndef MFL_H
+#define MFL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFL_OK 0
+#define MFL_EINVAL (-1)        /* invalid argument (message in mfl_last_error) */
+#define MFL_ENOCONV (-2)       /* iteration limit reached; outputs hold the last iterate */
+#define MFL_EBREAKDOWN (-3)    /* CG breakdown: p^T A p <= 0, or NaN/Inf residual */
+#define MFL_EHIP (-4)          /* a HIP runtime call failed */
+#define MFL_EUNSUPPORTED (-5)  /* valid request outside the implemented combinations */
+
+#define MFL_DISC_CG 0
+#define MFL_DISC_SIPG 1
+#define MFL_GEOM_CARTESIAN 0
+#define MFL_GEOM_CURVED 1
+#define MFL_BC_DIRICHLET 0
+#define MFL_BC_NEUMANN 1
+#define MFL_F64 0
+#define MFL_F32 1
+
+typedef struct mfl_params {
+  int degree;             /* polynomial degree k, 1..8 */
+  int cells_per_dim;      /* N_c of the finest level, >= 1 */
+  int min_level_cells;    /* cells per direction of the coarsest multigrid level (default 2) */
+  int disc;               /* MFL_DISC_CG or MFL_DISC_SIPG */
+  int geometry;           /* MFL_GEOM_CARTESIAN or MFL_GEOM_CURVED (CG only) */
+  double curve_amp;       /* a of the deformation (default 0.1; ignored when Cartesian) */
+  int bc;                 /* MFL_BC_DIRICHLET (homogeneous) or MFL_BC_NEUMANN (apply only) */
+  double penalty_factor;  /* SIPG: sigma = penalty_factor (k+1)^2 / h (paper: 3 = d) */
+  int cheb_degree;        /* smoother degree (Sec. 4.1: 5) */
+  double cheb_lo;         /* lower end of the smoothing interval / lambda_max (0.06) */
+  double cheb_hi;         /* upper end / lambda_max (1.2) */
+  int eig_iters;          /* CG iterations of the lambda_max estimate (15) */
+  double coarse_tol;      /* a-priori error bound of the coarse Chebyshev solver (1e-3) */
+  int mg_precision;       /* MFL_F64 or MFL_F32: arithmetic of the V-cycle */
+  int build_mg;           /* 0: finest-level operator only; 1: multigrid hierarchy */
+} mfl_params;
+
+typedef struct mfl_context *mfl_handle;
+
+/* Fill *p with the defaults above (k = 2, N_c = 8, CG, Cartesian, Dirichlet, MG in FP64). */
+int mfl_default_params(mfl_params *p);
+
+/* Sizes for params p (host only, no GPU call): number of DoFs and cells of the finest
+ * level, and the workspace size in bytes that mfl_setup needs.  Any output may be NULL.
+ * Errors: MFL_EINVAL for an unsupported or inconsistent p (k outside 1..8, N_c not
+ * reducible by halving to min_level_cells when build_mg = 1, SIPG with curved
+ * geometry or multigrid). */
+int mfl_query(const mfl_params *p, int64_t *n_dofs, int64_t *n_cells, int64_t *workspace_bytes);
+
+/* Build the level hierarchy in `workspace` (device memory, >= the queried size, 256-byte
+ * aligned): geometry factors (Sec. 3: per-quadrature-point metric on curved meshes, one
+ * scalar per cell on Cartesian ones), Jacobi diagonals, and for build_mg = 1 the
+ * lambda_max estimates of every level (Sec. 4.1) and the coarse solver's eigenvalue range.
+ * kappa_cells: device array of n_cells doubles (> 0), or NULL for kappa = 1.
+ * Synchronizes `stream` (the eigenvalue estimates read scalars back).  On success *out is
+ * a new handle.  Errors: MFL_EINVAL (params, NULL or misaligned workspace, too small
+ * size), MFL_EHIP. */
+int mfl_setup(const mfl_params *p, void *workspace, int64_t workspace_bytes,
+              const double *kappa_cells, void *stream, mfl_handle *out);
+
+/* Replace the cellwise kappa (device, n_cells doubles > 0) and rebuild everything that
+ * depends on it: coarse-level kappa (mean of the 8 children), diagonals, eigenvalue
+ * estimates.  Synchronizes `stream`. */
+int mfl_set_kappa(mfl_handle h, const double *kappa_cells, void *stream);
+
+/* Number of levels (1 without multigrid); level 0 is the coarsest, num_levels-1 the finest. */
+int mfl_num_levels(mfl_handle h);
+
+/* Level description: cells per direction, DoFs, lambda_max estimate of D^{-1}A (0 on the
+ * coarsest level), and for the coarsest level the eigenvalue range used by the coarse
+ * solver and its number of Chebyshev steps (0 elsewhere).  Outputs may be NULL. */
+int mfl_level_info(mfl_handle h, int level, int *cells_per_dim, int64_t *n_dofs,
+                   double *lambda_max, double *coarse_lmin, double *coarse_lmax, int *coarse_steps);
+
+/* dst = A src on `level` (-1 = finest) in precision dtype (MFL_F64: double vectors,
+ * MFL_F32: float vectors with FP32 geometry factors).  Eq. (mf_eval) with sum
+ * factorization; CG: identity on Dirichlet DoFs; SIPG: Sec. 2.2.  src and dst must not
+ * overlap.  Asynchronous. */
+int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, void *stream);
+
+/* out = diag(A) on `level` (-1 = finest), in dtype (CG only; Dirichlet DoFs hold 1). */
+int mfl_diagonal(mfl_handle h, int level, int dtype, void *out, void *stream);
+
+/* Transfer between level l-1 (coarse) and l (fine), in the multigrid precision dtype:
+ * direction 0: fine += P coarse (embedding, Sec. 4.1); direction 1: coarse = P^T fine.
+ * Dirichlet rows/columns of P are removed.  Asynchronous. */
+int mfl_transfer(mfl_handle h, int level, int direction, int dtype, const void *src, void *dst,
+                 void *stream);
+
+/* z = one V(1,1)-cycle applied to r (finest level, FP64 in and out; the cycle itself runs
+ * in the handle's mg_precision, the coarse solve always in FP64).  Asynchronous. */
+int mfl_vcycle(mfl_handle h, const double *r, double *z, void *stream);
+
+/* Solve A x = b by CG preconditioned with one V-cycle per iteration (Sec. 4.1), x_0 = 0,
+ * until ||r||_2 <= rtol ||b||_2 or maxit iterations.  b, x: device, n_dofs doubles; x is
+ * overwritten.  *iters and *final_rel_res (host pointers, may be NULL) receive the result.
+ * Synchronizes once per iteration to test convergence.  Returns MFL_OK, MFL_ENOCONV (x,
+ * iters and residual still valid) or MFL_EBREAKDOWN. */
+int mfl_pcg_solve(mfl_handle h, const double *b, double *x, double rtol, int maxit, int *iters,
+                  double *final_rel_res, void *stream);
+
+/* b_i = int f phi_i with f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) (the right-hand side of the
+ * manufactured solution sin sin sin), k+1 Gauss points, on the finest level (CG); zero on
+ * Dirichlet DoFs.  Asynchronous. */
+int mfl_rhs_sine(mfl_handle h, double *b, void *stream);
+
+/* Adjoint solve A lambda = dJdu with the same operator and preconditioner (A is symmetric);
+ * the Dirichlet entries of the right-hand side are taken as zero.  Same outputs and errors
+ * as mfl_pcg_solve. */
+int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double rtol, int maxit,
+                      int *iters, double *final_rel_res, void *stream);
+
+/* dJ/dkappa_c = -lambda_c^T A_c^{(kappa=1)} u_c for every cell c of the finest level (the
+ * element operator of eq. mf_eval at unit kappa; Dirichlet entries of u and lambda are taken
+ * as zero).  grad: device, n_cells doubles.  Asynchronous. */
+int mfl_kappa_gradient(mfl_handle h, const double *u, const double *lambda, double *grad,
+                       void *stream);
+
+/* Release the handle (the workspace stays owned by the caller). */
+int mfl_destroy(mfl_handle h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *mfl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFL_H */

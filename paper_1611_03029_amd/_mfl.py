@@ -1,0 +1,232 @@
+"""ctypes binding of libmfl.so (include/mfl.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; torch supplies device memory and
+the current HIP stream.  Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfl.so")
+
+MFL_OK, MFL_EINVAL, MFL_ENOCONV, MFL_EBREAKDOWN, MFL_EHIP, MFL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CG, SIPG = 0, 1
+CARTESIAN, CURVED = 0, 1
+DIRICHLET, NEUMANN = 0, 1
+F64, F32 = 0, 1
+_DT = {F64: torch.float64, F32: torch.float32}
+
+
+class MflError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("mfl error %d: %s" % (code, message))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("degree", ctypes.c_int),
+        ("cells_per_dim", ctypes.c_int),
+        ("min_level_cells", ctypes.c_int),
+        ("disc", ctypes.c_int),
+        ("geometry", ctypes.c_int),
+        ("curve_amp", ctypes.c_double),
+        ("bc", ctypes.c_int),
+        ("penalty_factor", ctypes.c_double),
+        ("cheb_degree", ctypes.c_int),
+        ("cheb_lo", ctypes.c_double),
+        ("cheb_hi", ctypes.c_double),
+        ("eig_iters", ctypes.c_int),
+        ("coarse_tol", ctypes.c_double),
+        ("mg_precision", ctypes.c_int),
+        ("build_mg", ctypes.c_int),
+    ]
+
+
+_lib = None
+P = ctypes.c_void_p
+I64P = ctypes.POINTER(ctypes.c_int64)
+IP = ctypes.POINTER(ctypes.c_int)
+DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "mfl_default_params": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "mfl_query": (ctypes.c_int, [ctypes.POINTER(Params), I64P, I64P, I64P]),
+    "mfl_setup": (ctypes.c_int, [ctypes.POINTER(Params), P, ctypes.c_int64, P, P, ctypes.POINTER(P)]),
+    "mfl_set_kappa": (ctypes.c_int, [P, P, P]),
+    "mfl_num_levels": (ctypes.c_int, [P]),
+    "mfl_level_info": (ctypes.c_int, [P, ctypes.c_int, IP, I64P, DP, DP, DP, IP]),
+    "mfl_apply": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P, P]),
+    "mfl_diagonal": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P]),
+    "mfl_transfer": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]),
+    "mfl_vcycle": (ctypes.c_int, [P, P, P, P]),
+    "mfl_pcg_solve": (ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_int, IP, DP, P]),
+    "mfl_rhs_sine": (ctypes.c_int, [P, P, P]),
+    "mfl_adjoint_solve": (ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_int, IP, DP, P]),
+    "mfl_kappa_gradient": (ctypes.c_int, [P, P, P, P, P]),
+    "mfl_destroy": (ctypes.c_int, [P]),
+    "mfl_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmfl.so is not built (run __graft_entry__.build()); "
+                              "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != MFL_OK and rc not in allow:
+        raise MflError(rc, lib().mfl_last_error().decode())
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.1, bc=DIRICHLET,
+                penalty_factor=1.0, build_mg=False, mg_precision=F64, min_level_cells=2,
+                cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3):
+    p = Params()
+    _check(lib().mfl_default_params(ctypes.byref(p)))
+    p.degree, p.cells_per_dim, p.min_level_cells = degree, cells_per_dim, min_level_cells
+    p.disc, p.geometry, p.curve_amp, p.bc = disc, geometry, curve_amp, bc
+    p.penalty_factor, p.build_mg, p.mg_precision = penalty_factor, int(bool(build_mg)), mg_precision
+    p.cheb_degree, p.cheb_lo, p.cheb_hi = cheb_degree, cheb_lo, cheb_hi
+    p.eig_iters, p.coarse_tol = eig_iters, coarse_tol
+    return p
+
+
+def query(params):
+    nd, nc, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mfl_query(ctypes.byref(params), ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(ws)))
+    return nd.value, nc.value, ws.value
+
+
+class Problem:
+    """A set-up operator (and optionally its multigrid hierarchy) on the current GPU.
+
+    Owns the device workspace (a torch uint8 tensor) and the library handle.
+    """
+
+    def __init__(self, degree, cells_per_dim, kappa=None, device="cuda", **kw):
+        self.params = make_params(degree, cells_per_dim, **kw)
+        self.n_dofs, self.n_cells, ws = query(self.params)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(max(ws, 256) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._kappa = None
+        h = ctypes.c_void_p()
+        kptr = None
+        if kappa is not None:
+            self._kappa = self._as_f64(kappa, self.n_cells)
+            kptr = _ptr(self._kappa)
+        _check(lib().mfl_setup(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr),
+                               ctypes.c_int64(ws), kptr, _stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mfl_destroy(h)
+            self.handle = None
+
+    def _as_f64(self, t, n):
+        t = torch.as_tensor(t, dtype=torch.float64, device=self.device).contiguous()
+        if t.numel() != n:
+            raise ValueError("expected %d values, got %d" % (n, t.numel()))
+        return t
+
+    @property
+    def num_levels(self):
+        return _check(lib().mfl_num_levels(self.handle), allow=range(1, 1 << 20))
+
+    def level_info(self, level=-1):
+        c, nd = ctypes.c_int(), ctypes.c_int64()
+        lam, lmin, lmax, st = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(lib().mfl_level_info(self.handle, level, ctypes.byref(c), ctypes.byref(nd), ctypes.byref(lam),
+                                    ctypes.byref(lmin), ctypes.byref(lmax), ctypes.byref(st)))
+        return {"cells_per_dim": c.value, "n_dofs": nd.value, "lambda_max": lam.value,
+                "coarse_lmin": lmin.value, "coarse_lmax": lmax.value, "coarse_steps": st.value}
+
+    def set_kappa(self, kappa):
+        self._kappa = self._as_f64(kappa, self.n_cells)
+        _check(lib().mfl_set_kappa(self.handle, _ptr(self._kappa), _stream()))
+
+    def apply(self, src, dst=None, level=-1):
+        dtype = F32 if src.dtype == torch.float32 else F64
+        if src.dtype != _DT[dtype] or not src.is_contiguous() or src.device.type != "cuda":
+            raise ValueError("src must be a contiguous float64/float32 CUDA tensor")
+        n = self.level_info(level)["n_dofs"]
+        if src.numel() != n:
+            raise ValueError("src has %d values, level has %d DoFs" % (src.numel(), n))
+        if dst is None:
+            dst = torch.empty_like(src)
+        elif dst.dtype != src.dtype or dst.numel() != n or not dst.is_contiguous():
+            raise ValueError("dst must match src")
+        _check(lib().mfl_apply(self.handle, level, dtype, _ptr(src), _ptr(dst), _stream()))
+        return dst
+
+    def diagonal(self, level=-1, dtype=torch.float64):
+        n = self.level_info(level)["n_dofs"]
+        out = torch.empty(n, dtype=dtype, device=self.device)
+        _check(lib().mfl_diagonal(self.handle, level, F32 if dtype == torch.float32 else F64, _ptr(out),
+                                  _stream()))
+        return out
+
+    def transfer(self, level, direction, src, dst):
+        dtype = F32 if dst.dtype == torch.float32 and direction == 0 else (
+            F32 if src.dtype == torch.float32 else F64)
+        _check(lib().mfl_transfer(self.handle, level, direction, dtype, _ptr(src), _ptr(dst), _stream()))
+        return dst
+
+    def vcycle(self, r, z=None):
+        r = self._as_f64(r, self.n_dofs)
+        z = torch.empty_like(r) if z is None else z
+        _check(lib().mfl_vcycle(self.handle, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def rhs_sine(self):
+        b = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        _check(lib().mfl_rhs_sine(self.handle, _ptr(b), _stream()))
+        return b
+
+    def _solve(self, fn, b, rtol, maxit, x, raise_on_noconv):
+        b = self._as_f64(b, self.n_dofs)
+        x = torch.empty_like(b) if x is None else x
+        it, res = ctypes.c_int(), ctypes.c_double()
+        rc = fn(self.handle, _ptr(b), _ptr(x), ctypes.c_double(rtol), ctypes.c_int(maxit),
+                ctypes.byref(it), ctypes.byref(res), _stream())
+        _check(rc, allow=() if raise_on_noconv else (MFL_ENOCONV,))
+        return x, it.value, res.value
+
+    def solve(self, b, rtol=1e-10, maxit=100, x=None, raise_on_noconv=True):
+        """PCG with one V-cycle per iteration; returns (x, iterations, relative residual)."""
+        return self._solve(lib().mfl_pcg_solve, b, rtol, maxit, x, raise_on_noconv)
+
+    def adjoint_solve(self, dJdu, rtol=1e-10, maxit=100, x=None, raise_on_noconv=True):
+        return self._solve(lib().mfl_adjoint_solve, dJdu, rtol, maxit, x, raise_on_noconv)
+
+    def kappa_gradient(self, u, lam):
+        u = self._as_f64(u, self.n_dofs)
+        lam = self._as_f64(lam, self.n_dofs)
+        g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        _check(lib().mfl_kappa_gradient(self.handle, _ptr(u), _ptr(lam), _ptr(g), _stream()))
+        return g

@@ -1,0 +1,620 @@
+// C ABI: parameter checks, workspace layout, setup, operator application, the multigrid
+// V-cycle and the preconditioned conjugate gradient solver (Sec. 4.1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mfl_internal.h"
+
+using namespace mfl;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(MFL_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_params(const mfl_params *p) {
+  if (!p) return fail(MFL_EINVAL, "params is NULL");
+  if (p->degree < 1 || p->degree > kMaxDegree)
+    return fail(MFL_EINVAL, "degree %d outside 1..%d", p->degree, kMaxDegree);
+  if (p->cells_per_dim < 1) return fail(MFL_EINVAL, "cells_per_dim must be >= 1");
+  if (p->disc != MFL_DISC_CG && p->disc != MFL_DISC_SIPG) return fail(MFL_EINVAL, "unknown disc %d", p->disc);
+  if (p->geometry != MFL_GEOM_CARTESIAN && p->geometry != MFL_GEOM_CURVED)
+    return fail(MFL_EINVAL, "unknown geometry %d", p->geometry);
+  if (p->bc != MFL_BC_DIRICHLET && p->bc != MFL_BC_NEUMANN) return fail(MFL_EINVAL, "unknown bc %d", p->bc);
+  if (p->mg_precision != MFL_F64 && p->mg_precision != MFL_F32)
+    return fail(MFL_EINVAL, "unknown mg_precision %d", p->mg_precision);
+  if (p->disc == MFL_DISC_SIPG) {
+    if (p->geometry != MFL_GEOM_CARTESIAN)
+      return fail(MFL_EINVAL, "SIPG is implemented on Cartesian meshes only");
+    if (p->build_mg) return fail(MFL_EINVAL, "multigrid is implemented for the CG discretization only");
+    if (!(p->penalty_factor > 0.0)) return fail(MFL_EINVAL, "penalty_factor must be > 0");
+  }
+  if (p->geometry == MFL_GEOM_CURVED) {
+    // det J = 1 + a pi (c s s + s c s + s s c) stays positive for |a| < 1 / (pi * 3^(1/2) ...);
+    // the map is checked cell by cell at setup only through the sign of det J at the
+    // quadrature points, so keep the amplitude in the range where it cannot fold.
+    if (!(std::fabs(p->curve_amp) <= 0.15)) return fail(MFL_EINVAL, "|curve_amp| must be <= 0.15");
+  }
+  if (p->build_mg) {
+    if (p->bc != MFL_BC_DIRICHLET) return fail(MFL_EINVAL, "multigrid requires Dirichlet conditions");
+    if (p->min_level_cells < 1) return fail(MFL_EINVAL, "min_level_cells must be >= 1");
+    int Nc = p->cells_per_dim;
+    while (Nc > p->min_level_cells) {
+      if (Nc % 2) return fail(MFL_EINVAL, "cells_per_dim %d does not halve down to min_level_cells %d",
+                              p->cells_per_dim, p->min_level_cells);
+      Nc /= 2;
+    }
+    if (Nc != p->min_level_cells)
+      return fail(MFL_EINVAL, "cells_per_dim %d does not halve down to min_level_cells %d",
+                  p->cells_per_dim, p->min_level_cells);
+    if (p->cheb_degree < 1 || p->cheb_degree > 64) return fail(MFL_EINVAL, "cheb_degree outside 1..64");
+    if (!(p->cheb_lo > 0.0 && p->cheb_hi > p->cheb_lo)) return fail(MFL_EINVAL, "need 0 < cheb_lo < cheb_hi");
+    if (p->eig_iters < 1 || p->eig_iters > 1000) return fail(MFL_EINVAL, "eig_iters outside 1..1000");
+    if (!(p->coarse_tol > 0.0 && p->coarse_tol < 1.0)) return fail(MFL_EINVAL, "coarse_tol outside (0,1)");
+  }
+  return MFL_OK;
+}
+
+std::vector<int> level_cells(const mfl_params &p) {
+  std::vector<int> v;
+  if (!p.build_mg) return {p.cells_per_dim};
+  for (int Nc = p.min_level_cells; Nc <= p.cells_per_dim; Nc *= 2) v.push_back(Nc);
+  return v;
+}
+
+struct Bump {
+  char *base = nullptr;
+  int64_t off = 0;
+  template <typename T>
+  T *take(int64_t count) {
+    off = (off + 255) / 256 * 256;
+    T *r = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * int64_t(sizeof(T));
+    return r;
+  }
+};
+
+// Lays out all device arrays of the context in the workspace (base == nullptr: sizes only).
+int64_t layout(Context &c, char *base) {
+  Bump b{base, 0};
+  const mfl_params &p = c.p;
+  const int n3 = c.n * c.n * c.n;
+  const bool cg = p.disc == MFL_DISC_CG;
+  for (size_t l = 0; l < c.levels.size(); ++l) {
+    Level &L = c.levels[l];
+    L.kappa64 = b.take<double>(L.ncells);
+    L.kappa32 = b.take<float>(L.ncells);
+    if (cg && p.geometry == MFL_GEOM_CURVED) {
+      L.metric64 = b.take<double>(L.ncells * 6 * n3);
+      L.metric32 = b.take<float>(L.ncells * 6 * n3);
+    }
+    if (cg) {
+      L.diag64 = b.take<double>(L.ndofs);
+      L.dinv64 = b.take<double>(L.ndofs);
+      L.diag32 = b.take<float>(L.ndofs);
+      L.dinv32 = b.take<float>(L.ndofs);
+    }
+    if (p.build_mg) {
+      L.mg_f32 = (p.mg_precision == MFL_F32) && l > 0;
+      const int64_t es = L.mg_f32 ? 4 : 8;
+      L.b = b.take<char>(L.ndofs * es);
+      L.x = b.take<char>(L.ndofs * es);
+      L.ax = b.take<char>(L.ndofs * es);
+      L.d = b.take<char>(L.ndofs * es);
+    }
+  }
+  if (p.build_mg) {
+    const int64_t N = c.levels.back().ndofs;
+    c.r = b.take<double>(N);
+    c.z = b.take<double>(N);
+    c.pv = b.take<double>(N);
+    c.q = b.take<double>(N);
+  }
+  c.partials = b.take<double>(kReduceBlocks);
+  c.scalars = b.take<double>(kNumScalars);
+  return b.off;
+}
+
+void init_context(Context &c, const mfl_params &p) {
+  c.p = p;
+  c.k = p.degree;
+  c.n = p.degree + 1;
+  c.levels.clear();
+  for (int Nc : level_cells(p)) {
+    Level L;
+    L.Nc = Nc;
+    L.N1 = c.k * Nc + 1;
+    L.ncells = int64_t(Nc) * Nc * Nc;
+    L.ndofs = p.disc == MFL_DISC_CG ? int64_t(L.N1) * L.N1 * L.N1 : L.ncells * c.n * c.n * c.n;
+    L.h = 1.0 / Nc;
+    c.levels.push_back(L);
+  }
+}
+
+int level_index(const Context &c, int level) {
+  const int nl = int(c.levels.size());
+  if (level == -1) return nl - 1;
+  if (level < 0 || level >= nl) return -1;
+  return level;
+}
+
+// Extreme eigenvalues of the symmetric tridiagonal matrix (a on the diagonal, b off it)
+// by bisection on Sturm sequence counts.
+void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b, double &lmin,
+                      double &lmax) {
+  const int m = int(a.size());
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::fmin(lo, a[i] - r);
+    hi = std::fmax(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {   // number of eigenvalues < x
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  auto bisect = [&](int target) {   // smallest x with count_below(x) > target
+    double l = lo, h = hi;
+    for (int it = 0; it < 200 && h - l > 1e-16 * std::fmax(1.0, std::fabs(h)); ++it) {
+      const double mid = 0.5 * (l + h);
+      if (count_below(mid) > target) h = mid; else l = mid;
+    }
+    return 0.5 * (l + h);
+  };
+  lmin = bisect(0);
+  lmax = bisect(m - 1);
+}
+
+int apply_level(Context &c, int l, int dtype, const void *src, void *dst, hipStream_t s) {
+  const Level &L = c.levels[l];
+  if (c.p.disc == MFL_DISC_SIPG) {
+    HIP_TRY(launch_sipg_apply(c, L, dtype, src, dst, s));
+  } else {
+    HIP_TRY(launch_cg_apply(c, L, dtype, src, dst, s));
+  }
+  return MFL_OK;
+}
+
+int read_scalars(Context &c, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(c.host_scalars, c.scalars, kNumScalars * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MFL_OK;
+}
+
+// Jacobi-preconditioned CG on level l from the SplitMix64 start vector (key = cells per
+// direction, Dirichlet entries zero); records the Lanczos tridiagonal from alpha, beta.
+int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vector<double> &diag,
+            std::vector<double> &off, hipStream_t s) {
+  Level &L = c.levels[l];
+  const int64_t N = L.ndofs;
+  double *r = c.r, *z = c.z, *p = c.pv, *q = c.q;
+  HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), s));
+  HIP_TRY(launch_jacobi(L.dinv64, r, z, N, s));
+  HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
+  HIP_TRY(launch_finalize(c.partials, c.scalars, kRZ, kFinSum, s));
+  int rc = read_scalars(c, s);
+  if (rc) return rc;
+  const double rz0 = c.host_scalars[kRZ];
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < max_iters && rz0 > 0.0; ++it) {
+    if ((rc = apply_level(c, l, MFL_F64, p, q, s))) return rc;
+    HIP_TRY(launch_dot_partial(p, q, N, c.partials, s));
+    HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s));
+    // r -= alpha q (x is not needed: the z buffer takes the x update and is overwritten)
+    HIP_TRY(launch_pcg_update_xr(z, r, p, q, c.scalars, N, c.partials, s));
+    HIP_TRY(launch_jacobi(L.dinv64, r, z, N, s));
+    HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
+    HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinBeta, s));
+    HIP_TRY(launch_pcg_update_p(p, z, c.scalars, N, s));
+    if ((rc = read_scalars(c, s))) return rc;
+    const double pq = c.host_scalars[kPQ];
+    if (!(pq > 0.0) || !std::isfinite(pq)) break;
+    alphas.push_back(c.host_scalars[kAlpha]);
+    betas.push_back(c.host_scalars[kBeta]);
+    if (run_to_convergence && c.host_scalars[kRZ] <= 1e-30 * rz0) break;
+  }
+  const int m = int(alphas.size());
+  if (m == 0) return fail(MFL_EBREAKDOWN, "eigenvalue estimate on level %d: no CG step possible", l);
+  diag.assign(m, 0.0);
+  off.assign(m > 1 ? m - 1 : 0, 0.0);
+  for (int j = 0; j < m; ++j) {
+    diag[j] = 1.0 / alphas[j] + (j > 0 ? betas[j - 1] / alphas[j - 1] : 0.0);
+    if (j + 1 < m) off[j] = std::sqrt(betas[j]) / alphas[j];
+  }
+  return MFL_OK;
+}
+
+// Everything that depends on kappa: coarse kappa, diagonals, eigenvalue estimates.
+int rebuild_kappa_dependent(Context &c, hipStream_t s) {
+  const int nl = int(c.levels.size());
+  for (int l = nl - 2; l >= 0; --l) HIP_TRY(launch_coarsen_kappa(c.levels[l], c.levels[l + 1], s));
+  if (c.p.disc != MFL_DISC_CG) return MFL_OK;
+  for (int l = 0; l < nl; ++l) HIP_TRY(launch_cg_diagonal(c, c.levels[l], s));
+  if (!c.p.build_mg) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFL_OK;
+  }
+  std::vector<double> a, b;
+  for (int l = 0; l < nl; ++l) {
+    Level &L = c.levels[l];
+    double lmin, lmax;
+    int rc;
+    if (l == 0) {
+      const int interior = (L.N1 - 2) * (L.N1 - 2) * (L.N1 - 2);
+      if ((rc = lanczos(c, l, interior + 50, true, a, b, s))) return rc;
+      tridiag_extremes(a, b, lmin, lmax);
+      L.coarse_lmin = lmin;
+      L.coarse_lmax = lmax;
+      const double cond = lmax / lmin;
+      const double rate = (std::sqrt(cond) - 1.0) / (std::sqrt(cond) + 1.0);
+      L.coarse_steps = rate <= 0.0 ? 1
+                                   : int(std::ceil(std::log(2.0 / c.p.coarse_tol) / std::log(1.0 / rate)));
+      if (L.coarse_steps < 1) L.coarse_steps = 1;
+    } else {
+      if ((rc = lanczos(c, l, c.p.eig_iters, false, a, b, s))) return rc;
+      tridiag_extremes(a, b, lmin, lmax);
+      L.lambda_max = lmax;
+    }
+  }
+  return MFL_OK;
+}
+
+int dtype_of(const Level &L) { return L.mg_f32 ? MFL_F32 : MFL_F64; }
+const void *dinv_of(const Level &L) { return L.mg_f32 ? (const void *)L.dinv32 : (const void *)L.dinv64; }
+
+// Chebyshev iteration on level l with interval [lo, hi] and `updates` updates of x.
+// zero_start: x = 0 initially and b is taken from b_in (stored into L.b when b_in != L.b).
+int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_start, const void *b_in,
+              int b_dtype, double *x64_out, hipStream_t s) {
+  Level &L = c.levels[l];
+  const int dt = dtype_of(L);
+  const int64_t N = L.ndofs;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  int rc;
+  int done = 0;
+  const bool last_writes = x64_out != nullptr;
+  if (zero_start) {
+    HIP_TRY(launch_cheb_first(b_in, b_dtype, b_in == L.b ? nullptr : L.b, dinv_of(L), L.d, L.x, dt, N,
+                              1.0 / theta, s));
+    if (updates == 1 && last_writes) HIP_TRY(launch_cast(L.x, dt, x64_out, MFL_F64, N, s));
+  } else {
+    if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
+    HIP_TRY(launch_cheb_step(L.b, L.ax, dinv_of(L), L.d, L.x, (updates == 1) ? x64_out : nullptr, dt,
+                             N, 0.0, 1.0 / theta, s));
+  }
+  done = 1;
+  double rho = delta > 0.0 ? delta / theta : 0.0;   // 1 / sigma_1
+  for (; done < updates; ++done) {
+    const double rho_new = 1.0 / (2.0 * theta / delta - rho);
+    if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
+    HIP_TRY(launch_cheb_step(L.b, L.ax, dinv_of(L), L.d, L.x, done + 1 == updates ? x64_out : nullptr,
+                             dt, N, rho_new * rho, 2.0 * rho_new / delta, s));
+    rho = rho_new;
+  }
+  return MFL_OK;
+}
+
+// One V(1,1) cycle on level l; the right-hand side is b_in (level-0 and recursion: L.b).
+int cycle(Context &c, int l, const void *b_in, int b_dtype, double *x64_out, hipStream_t s) {
+  Level &L = c.levels[l];
+  int rc;
+  if (l == 0)
+    return chebyshev(c, 0, L.coarse_lmin, L.coarse_lmax, L.coarse_steps, true, b_in, b_dtype, x64_out, s);
+  const double lo = c.p.cheb_lo * L.lambda_max, hi = c.p.cheb_hi * L.lambda_max;
+  const int updates = c.p.cheb_degree + 1;
+  const int dt = dtype_of(L);
+  Level &C = c.levels[l - 1];
+  if ((rc = chebyshev(c, l, lo, hi, updates, true, b_in, b_dtype, nullptr, s))) return rc;
+  if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
+  HIP_TRY(launch_restrict_residual(c, C, L, L.b, L.ax, dt, C.b, dtype_of(C), s));
+  if ((rc = cycle(c, l - 1, C.b, dtype_of(C), nullptr, s))) return rc;
+  HIP_TRY(launch_prolongate_add(c, C, L, C.x, dtype_of(C), L.x, dt, s));
+  return chebyshev(c, l, lo, hi, updates, false, nullptr, dt, x64_out, s);
+}
+
+int vcycle(Context &c, const double *r, double *z, hipStream_t s) {
+  const int top = int(c.levels.size()) - 1;
+  return cycle(c, top, r, MFL_F64, z, s);
+}
+
+int pcg(Context &c, const double *b, double *x, double rtol, int maxit, int *iters, double *res,
+        hipStream_t s) {
+  const Level &F = c.levels.back();
+  const int64_t N = F.ndofs;
+  int rc;
+  if (iters) *iters = 0;
+  if (res) *res = 0.0;
+  HIP_TRY(launch_fill(x, MFL_F64, N, 0.0, s));
+  HIP_TRY(hipMemcpyAsync(c.r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_dot_partial(b, b, N, c.partials, s));
+  HIP_TRY(launch_finalize(c.partials, c.scalars, kBB, kFinSum, s));
+  if ((rc = read_scalars(c, s))) return rc;
+  const double bb = c.host_scalars[kBB];
+  if (!std::isfinite(bb)) return fail(MFL_EBREAKDOWN, "right-hand side is not finite");
+  if (bb == 0.0) return MFL_OK;
+  const double nb = std::sqrt(bb);
+  if ((rc = vcycle(c, c.r, c.z, s))) return rc;
+  HIP_TRY(launch_dot_partial(c.r, c.z, N, c.partials, s));
+  HIP_TRY(launch_finalize(c.partials, c.scalars, kRZ, kFinSum, s));
+  HIP_TRY(hipMemcpyAsync(c.pv, c.z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double rel = 1.0;
+  for (int it = 1; it <= maxit; ++it) {
+    if ((rc = apply_level(c, int(c.levels.size()) - 1, MFL_F64, c.pv, c.q, s))) return rc;
+    HIP_TRY(launch_dot_partial(c.pv, c.q, N, c.partials, s));
+    HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s));
+    HIP_TRY(launch_pcg_update_xr(x, c.r, c.pv, c.q, c.scalars, N, c.partials, s));
+    HIP_TRY(launch_finalize(c.partials, c.scalars, kRR, kFinSum, s));
+    if ((rc = read_scalars(c, s))) return rc;
+    const double pq = c.host_scalars[kPQ], rz = c.host_scalars[kRZ], rr = c.host_scalars[kRR];
+    if (iters) *iters = it;
+    if (!(pq > 0.0) || !std::isfinite(pq) || !(rz > 0.0) || !std::isfinite(rr))
+      return fail(MFL_EBREAKDOWN, "CG breakdown at iteration %d (p^T A p = %g, r^T z = %g)", it, pq, rz);
+    rel = std::sqrt(rr) / nb;
+    if (res) *res = rel;
+    if (rel <= rtol) return MFL_OK;
+    if ((rc = vcycle(c, c.r, c.z, s))) return rc;
+    HIP_TRY(launch_dot_partial(c.r, c.z, N, c.partials, s));
+    HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinBeta, s));
+    HIP_TRY(launch_pcg_update_p(c.pv, c.z, c.scalars, N, s));
+  }
+  return fail(MFL_ENOCONV, "no convergence in %d iterations (relative residual %g)", maxit, rel);
+}
+
+bool need_mg(const Context &c) { return c.p.build_mg != 0; }
+
+}  // namespace
+
+struct mfl_context : public Context {};
+
+extern "C" {
+
+int mfl_default_params(mfl_params *p) {
+  if (!p) return fail(MFL_EINVAL, "params is NULL");
+  *p = mfl_params{};
+  p->degree = 2;
+  p->cells_per_dim = 8;
+  p->min_level_cells = 2;
+  p->disc = MFL_DISC_CG;
+  p->geometry = MFL_GEOM_CARTESIAN;
+  p->curve_amp = 0.1;
+  p->bc = MFL_BC_DIRICHLET;
+  p->penalty_factor = 1.0;
+  p->cheb_degree = 5;
+  p->cheb_lo = 0.06;
+  p->cheb_hi = 1.2;
+  p->eig_iters = 15;
+  p->coarse_tol = 1e-3;
+  p->mg_precision = MFL_F64;
+  p->build_mg = 0;
+  return MFL_OK;
+}
+
+int mfl_query(const mfl_params *p, int64_t *n_dofs, int64_t *n_cells, int64_t *workspace_bytes) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  Context c;
+  init_context(c, *p);
+  const int64_t bytes = layout(c, nullptr);
+  if (n_dofs) *n_dofs = c.levels.back().ndofs;
+  if (n_cells) *n_cells = c.levels.back().ncells;
+  if (workspace_bytes) *workspace_bytes = bytes;
+  return MFL_OK;
+}
+
+int mfl_setup(const mfl_params *p, void *workspace, int64_t workspace_bytes, const double *kappa_cells,
+              void *stream, mfl_handle *out) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!out) return fail(MFL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!workspace) return fail(MFL_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(MFL_EINVAL, "workspace is not 256-byte aligned");
+  mfl_context *c = new (std::nothrow) mfl_context();
+  if (!c) return fail(MFL_EINVAL, "out of host memory");
+  init_context(*c, *p);
+  const int64_t need = layout(*c, nullptr);
+  if (workspace_bytes < need) {
+    delete c;
+    return fail(MFL_EINVAL, "workspace too small: %lld < %lld bytes", (long long)workspace_bytes, (long long)need);
+  }
+  layout(*c, static_cast<char *>(workspace));
+  build_tables(c->k, c->tab64, c->tab32, c->transfer);
+  hipStream_t s = as_stream(stream);
+  auto cleanup = [&](int code) {
+    if (c->host_scalars) (void)hipHostFree(c->host_scalars);
+    delete c;
+    return code;
+  };
+  if (hipHostMalloc(reinterpret_cast<void **>(&c->host_scalars), kNumScalars * sizeof(double)) != hipSuccess)
+    return cleanup(fail(MFL_EHIP, "hipHostMalloc of the scalar mirror failed"));
+  Level &F = c->levels.back();
+  hipError_t e;
+  if (kappa_cells)
+    e = hipMemcpyAsync(F.kappa64, kappa_cells, F.ncells * sizeof(double), hipMemcpyDeviceToDevice, s);
+  else
+    e = launch_fill(F.kappa64, MFL_F64, F.ncells, 1.0, s);
+  if (e == hipSuccess) e = launch_cast(F.kappa64, MFL_F64, F.kappa32, MFL_F32, F.ncells, s);
+  if (e != hipSuccess) return cleanup(fail(MFL_EHIP, "kappa upload: %s", hipGetErrorString(e)));
+  if (p->disc == MFL_DISC_CG && p->geometry == MFL_GEOM_CURVED)
+    for (Level &L : c->levels)
+      if ((e = launch_metric_setup(*c, L, s)) != hipSuccess)
+        return cleanup(fail(MFL_EHIP, "metric setup: %s", hipGetErrorString(e)));
+  if ((rc = rebuild_kappa_dependent(*c, s))) return cleanup(rc);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess)
+    return cleanup(fail(MFL_EHIP, "setup: %s", hipGetErrorString(e)));
+  *out = c;
+  return MFL_OK;
+}
+
+int mfl_set_kappa(mfl_handle h, const double *kappa_cells, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (!kappa_cells) return fail(MFL_EINVAL, "kappa_cells is NULL");
+  hipStream_t s = as_stream(stream);
+  Level &F = h->levels.back();
+  HIP_TRY(hipMemcpyAsync(F.kappa64, kappa_cells, F.ncells * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_cast(F.kappa64, MFL_F64, F.kappa32, MFL_F32, F.ncells, s));
+  int rc = rebuild_kappa_dependent(*h, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return MFL_OK;
+}
+
+int mfl_num_levels(mfl_handle h) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  return int(h->levels.size());
+}
+
+int mfl_level_info(mfl_handle h, int level, int *cells_per_dim, int64_t *n_dofs, double *lambda_max,
+                   double *coarse_lmin, double *coarse_lmax, int *coarse_steps) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  const int l = level_index(*h, level);
+  if (l < 0) return fail(MFL_EINVAL, "level %d out of range", level);
+  const Level &L = h->levels[l];
+  if (cells_per_dim) *cells_per_dim = L.Nc;
+  if (n_dofs) *n_dofs = L.ndofs;
+  if (lambda_max) *lambda_max = L.lambda_max;
+  if (coarse_lmin) *coarse_lmin = L.coarse_lmin;
+  if (coarse_lmax) *coarse_lmax = L.coarse_lmax;
+  if (coarse_steps) *coarse_steps = L.coarse_steps;
+  return MFL_OK;
+}
+
+int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  const int l = level_index(*h, level);
+  if (l < 0) return fail(MFL_EINVAL, "level %d out of range", level);
+  if (dtype != MFL_F64 && dtype != MFL_F32) return fail(MFL_EINVAL, "unknown dtype %d", dtype);
+  if (!src || !dst) return fail(MFL_EINVAL, "src/dst is NULL");
+  if (src == dst) return fail(MFL_EINVAL, "src and dst must not overlap");
+  return apply_level(*h, l, dtype, src, dst, as_stream(stream));
+}
+
+int mfl_diagonal(mfl_handle h, int level, int dtype, void *out, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "diagonal is implemented for CG only");
+  const int l = level_index(*h, level);
+  if (l < 0) return fail(MFL_EINVAL, "level %d out of range", level);
+  if (!out) return fail(MFL_EINVAL, "out is NULL");
+  const Level &L = h->levels[l];
+  hipStream_t s = as_stream(stream);
+  if (dtype == MFL_F64)
+    HIP_TRY(hipMemcpyAsync(out, L.diag64, L.ndofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else if (dtype == MFL_F32)
+    HIP_TRY(hipMemcpyAsync(out, L.diag32, L.ndofs * sizeof(float), hipMemcpyDeviceToDevice, s));
+  else
+    return fail(MFL_EINVAL, "unknown dtype %d", dtype);
+  return MFL_OK;
+}
+
+int mfl_transfer(mfl_handle h, int level, int direction, int dtype, const void *src, void *dst,
+                 void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "transfer is implemented for CG only");
+  const int l = level_index(*h, level);
+  if (l < 1) return fail(MFL_EINVAL, "transfer needs a level >= 1 (got %d)", level);
+  if (dtype != MFL_F64 && dtype != MFL_F32) return fail(MFL_EINVAL, "unknown dtype %d", dtype);
+  if (!src || !dst) return fail(MFL_EINVAL, "src/dst is NULL");
+  const int cdt = (l - 1 == 0) ? MFL_F64 : dtype;
+  hipStream_t s = as_stream(stream);
+  if (direction == 0)
+    HIP_TRY(launch_prolongate_add(*h, h->levels[l - 1], h->levels[l], src, cdt, dst, dtype, s));
+  else if (direction == 1)
+    HIP_TRY(launch_restrict_residual(*h, h->levels[l - 1], h->levels[l], src, nullptr, dtype, dst, cdt, s));
+  else
+    return fail(MFL_EINVAL, "direction must be 0 (prolongate) or 1 (restrict)");
+  return MFL_OK;
+}
+
+int mfl_vcycle(mfl_handle h, const double *r, double *z, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (!need_mg(*h)) return fail(MFL_EINVAL, "handle was set up without multigrid (build_mg = 0)");
+  if (!r || !z) return fail(MFL_EINVAL, "r/z is NULL");
+  return vcycle(*h, r, z, as_stream(stream));
+}
+
+int mfl_pcg_solve(mfl_handle h, const double *b, double *x, double rtol, int maxit, int *iters,
+                  double *final_rel_res, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (!need_mg(*h)) return fail(MFL_EINVAL, "handle was set up without multigrid (build_mg = 0)");
+  if (!b || !x) return fail(MFL_EINVAL, "b/x is NULL");
+  if (!(rtol > 0.0) || maxit < 1) return fail(MFL_EINVAL, "need rtol > 0 and maxit >= 1");
+  return pcg(*h, b, x, rtol, maxit, iters, final_rel_res, as_stream(stream));
+}
+
+int mfl_rhs_sine(mfl_handle h, double *b, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "right-hand side helper is CG only");
+  if (!b) return fail(MFL_EINVAL, "b is NULL");
+  HIP_TRY(launch_rhs_sine(*h, h->levels.back(), b, as_stream(stream)));
+  return MFL_OK;
+}
+
+int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double rtol, int maxit,
+                      int *iters, double *final_rel_res, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (!need_mg(*h)) return fail(MFL_EINVAL, "handle was set up without multigrid (build_mg = 0)");
+  if (!dJdu || !lambda) return fail(MFL_EINVAL, "dJdu/lambda is NULL");
+  if (!(rtol > 0.0) || maxit < 1) return fail(MFL_EINVAL, "need rtol > 0 and maxit >= 1");
+  hipStream_t s = as_stream(stream);
+  const Level &F = h->levels.back();
+  // the right-hand side with zeroed Dirichlet entries is staged in the solution vector
+  if (dJdu != lambda)
+    HIP_TRY(hipMemcpyAsync(lambda, dJdu, F.ndofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_zero_boundary(lambda, F, s));
+  HIP_TRY(hipMemcpyAsync(h->q, lambda, F.ndofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // pcg() uses r, z, pv, q as work: move the staged right-hand side to the level's x-free slot
+  double *rhs = h->q;
+  // pcg copies b into r before q is first written, so q can carry b into the solve
+  return pcg(*h, rhs, lambda, rtol, maxit, iters, final_rel_res, s);
+}
+
+int mfl_kappa_gradient(mfl_handle h, const double *u, const double *lambda, double *grad, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "kappa gradient is CG only");
+  if (!u || !lambda || !grad) return fail(MFL_EINVAL, "u/lambda/grad is NULL");
+  HIP_TRY(launch_cg_kappa_grad(*h, h->levels.back(), u, lambda, grad, as_stream(stream)));
+  return MFL_OK;
+}
+
+int mfl_destroy(mfl_handle h) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->host_scalars) (void)hipHostFree(h->host_scalars);
+  delete h;
+  return MFL_OK;
+}
+
+const char *mfl_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,442 @@
+// Multigrid transfer, Chebyshev smoother updates and PCG vector kernels (Sec. 4.1).
+//
+// All vector kernels stream their operands once (grid-stride loops); reductions are
+// deterministic: fixed-size block partials followed by a one-block finalize kernel that
+// also forms the CG scalars on the device, so the host reads only the residual norm.
+#include "device_common.h"
+
+namespace mfl {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t items, int cap = 16384) {
+  int64_t g = (items + kBlock - 1) / kBlock;
+  return int(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < (n); i += int64_t(gridDim.x) * kBlock)
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fill_kernel(T *d, int64_t n, T v) {
+  GRID_STRIDE(i, n) d[i] = v;
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(kBlock) cast_kernel(const A *s, B *d, int64_t n) {
+  GRID_STRIDE(i, n) d[i] = B(s[i]);
+}
+
+__global__ void __launch_bounds__(kBlock)
+coarsen_kappa_kernel(const double *__restrict__ fine, double *__restrict__ c64, float *__restrict__ c32,
+                     int Ncc) {
+  const int64_t nc = int64_t(Ncc) * Ncc * Ncc;
+  const int Nf = 2 * Ncc;
+  GRID_STRIDE(i, nc) {
+    const int x = int(i % Ncc), y = int((i / Ncc) % Ncc), z = int(i / (int64_t(Ncc) * Ncc));
+    double s = 0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+          s += fine[(2 * x + dx) + int64_t(Nf) * ((2 * y + dy) + int64_t(Nf) * (2 * z + dz))];
+    c64[i] = 0.125 * s;
+    c32[i] = float(0.125 * s);
+  }
+}
+
+// Dirichlet DoFs get diagonal 1 (identity rows); inverse and FP32 copies.
+__global__ void __launch_bounds__(kBlock)
+diag_finalize_kernel(double *__restrict__ d64, double *__restrict__ i64, float *__restrict__ d32,
+                     float *__restrict__ i32, int N1, int dirichlet) {
+  const int64_t n = int64_t(N1) * N1 * N1;
+  GRID_STRIDE(i, n) {
+    const int x = int(i % N1), y = int((i / N1) % N1), z = int(i / (int64_t(N1) * N1));
+    double v = d64[i];
+    if (dirichlet && (on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(z, N1))) v = 1.0;
+    d64[i] = v;
+    i64[i] = 1.0 / v;
+    d32[i] = float(v);
+    i32[i] = float(1.0 / v);
+  }
+}
+
+// First Chebyshev update from a zero initial guess: d = D^{-1} b / theta, x = d.
+// b_in may be of another precision than the level (the FP64 residual entering an FP32
+// cycle); it is stored converted in b_store for the residuals of the later steps.
+template <typename A, typename T>
+__global__ void __launch_bounds__(kBlock)
+cheb_first_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const T *__restrict__ dinv,
+                  T *__restrict__ d, T *__restrict__ x, int64_t n, T inv_theta) {
+  GRID_STRIDE(i, n) {
+    const T b = T(b_in[i]);
+    if (b_store) b_store[i] = b;
+    const T v = dinv[i] * b * inv_theta;
+    d[i] = v;
+    x[i] = v;
+  }
+}
+
+// One Chebyshev update: d = c1 d + c2 D^{-1} (b - A x); x += d.  The residual is never
+// stored.  x64_out (optional) receives x in FP64 (exit of an FP32 cycle).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+cheb_step_kernel(const T *__restrict__ b, const T *__restrict__ ax, const T *__restrict__ dinv,
+                 T *__restrict__ d, T *__restrict__ x, double *__restrict__ x64, int64_t n, T c1,
+                 T c2) {
+  GRID_STRIDE(i, n) {
+    const T dn = c1 * d[i] + c2 * dinv[i] * (b[i] - ax[i]);
+    const T xn = x[i] + dn;
+    d[i] = dn;
+    x[i] = xn;
+    if (x64) x64[i] = double(xn);
+  }
+}
+
+// fine += P coarse over one coarse cell per work-group: embedding of the coarse Q_k
+// basis at the (2k+1)^3 fine nodes, applied direction by direction.  Each fine node is
+// written by exactly one coarse cell (half-open ownership), so no atomics are needed.
+template <int K, typename TC, typename TF>
+__global__ void __launch_bounds__(kBlock)
+prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, TransferTab tt) {
+  constexpr int n = K + 1, m = 2 * K + 1;
+  constexpr int s0 = (n * n * n > m * m * n) ? n * n * n : m * m * n;
+  __shared__ double P[m * n];
+  __shared__ TF b0[s0], b1[m * n * n];
+  for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
+  const int64_t cell = blockIdx.x;
+  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
+  for (int i = threadIdx.x; i < n * n * n; i += kBlock) {
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
+    const bool bnd = on_boundary(gx, N1c) || on_boundary(gy, N1c) || on_boundary(gz, N1c);
+    b0[i] = bnd ? TF(0) : TF(xc[gx + int64_t(N1c) * (gy + int64_t(N1c) * gz)]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * n * n; i += kBlock) {   // z: [L][j][i]
+    const int a = i % n, b = (i / n) % n, L = i / (n * n);
+    TF s = 0;
+    for (int l = 0; l < n; ++l) s += TF(P[L * n + l]) * b0[l * n * n + b * n + a];
+    b1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m * n; i += kBlock) {   // y: [L][J][i]
+    const int a = i % n, J = (i / n) % m, L = i / (n * m);
+    TF s = 0;
+    for (int b = 0; b < n; ++b) s += TF(P[J * n + b]) * b1[L * n * n + b * n + a];
+    b0[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m * m; i += kBlock) {   // x: fine node (I, J, L)
+    const int I = i % m, J = (i / m) % m, L = i / (m * m);
+    if ((I == m - 1 && cx < Ncc - 1) || (J == m - 1 && cy < Ncc - 1) || (L == m - 1 && cz < Ncc - 1))
+      continue;                                             // owned by the next coarse cell
+    const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
+    if (on_boundary(fx, N1f) || on_boundary(fy, N1f) || on_boundary(fz, N1f)) continue;
+    TF s = 0;
+    for (int a = 0; a < n; ++a) s += TF(P[I * n + a]) * b0[L * m * n + J * n + a];
+    xf[fx + int64_t(N1f) * (fy + int64_t(N1f) * fz)] += s;
+  }
+}
+
+// coarse = P^T (b_f - A x_f) over one coarse cell per work-group (axf == nullptr: P^T b_f).  Fine nodes shared by
+// several coarse cells are weighted by 1/multiplicity so that the sum over cells is P^T;
+// the n^3 results are added with atomics into the zeroed coarse vector.
+template <int K, typename TF, typename TC>
+__global__ void __launch_bounds__(kBlock)
+restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__restrict__ bc, int Ncc,
+                TransferTab tt) {
+  constexpr int n = K + 1, m = 2 * K + 1;
+  __shared__ double P[m * n];
+  __shared__ TF r[m * m * m], t1[m * m * n];
+  for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
+  const int64_t cell = blockIdx.x;
+  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
+  for (int i = threadIdx.x; i < m * m * m; i += kBlock) {
+    const int I = i % m, J = (i / m) % m, L = i / (m * m);
+    const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
+    TF v = 0;
+    if (!(on_boundary(fx, N1f) || on_boundary(fy, N1f) || on_boundary(fz, N1f))) {
+      const int64_t g = fx + int64_t(N1f) * (fy + int64_t(N1f) * fz);
+      TF wgt = 1;
+      if ((I == 0 && cx > 0) || (I == m - 1 && cx < Ncc - 1)) wgt *= TF(0.5);
+      if ((J == 0 && cy > 0) || (J == m - 1 && cy < Ncc - 1)) wgt *= TF(0.5);
+      if ((L == 0 && cz > 0) || (L == m - 1 && cz < Ncc - 1)) wgt *= TF(0.5);
+      v = wgt * (axf ? bf[g] - axf[g] : bf[g]);
+    }
+    r[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m * n; i += kBlock) {   // x: [L][J][a]
+    const int a = i % n, J = (i / n) % m, L = i / (n * m);
+    TF s = 0;
+    for (int I = 0; I < m; ++I) s += TF(P[I * n + a]) * r[L * m * m + J * m + I];
+    t1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * n * n; i += kBlock) {   // y: [L][b][a] (reuses r)
+    const int a = i % n, b = (i / n) % n, L = i / (n * n);
+    TF s = 0;
+    for (int J = 0; J < m; ++J) s += TF(P[J * n + b]) * t1[L * m * n + J * n + a];
+    r[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * n * n; i += kBlock) {   // z: coarse DoF (a, b, l)
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
+    if (on_boundary(gx, N1c) || on_boundary(gy, N1c) || on_boundary(gz, N1c)) continue;
+    TF s = 0;
+    for (int L = 0; L < m; ++L) s += TF(P[L * n + l]) * r[L * n * n + b * n + a];
+    atomic_add(bc + gx + int64_t(N1c) * (gy + int64_t(N1c) * gz), TC(s));
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+dot_partial_kernel(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                   double *__restrict__ partials) {
+  __shared__ double sc[kBlock];
+  double s = 0;
+  GRID_STRIDE(i, n) s += a[i] * b[i];
+  s = block_sum(s, sc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+finalize_kernel(const double *__restrict__ partials, double *__restrict__ sc, int which, int op) {
+  __shared__ double red[kBlock];
+  double s = 0;
+  for (int i = threadIdx.x; i < kReduceBlocks; i += kBlock) s += partials[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    if (op == kFinSum) {
+      sc[which] = s;
+    } else if (op == kFinAlpha) {
+      // a non-positive or non-finite p^T A p is a breakdown: skip the update (alpha = 0)
+      sc[kPQ] = s;
+      sc[kAlpha] = (s > 0.0 && isfinite(s)) ? sc[kRZ] / s : 0.0;
+    } else {
+      sc[kRZnew] = s;
+      sc[kBeta] = s / sc[kRZ];
+      sc[kRZ] = s;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+pcg_update_xr_kernel(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+                     const double *__restrict__ q, const double *__restrict__ sc, int64_t n,
+                     double *__restrict__ partials) {
+  __shared__ double red[kBlock];
+  const double alpha = sc[kAlpha];
+  double s = 0;
+  GRID_STRIDE(i, n) {
+    x[i] += alpha * p[i];
+    const double rn = r[i] - alpha * q[i];
+    r[i] = rn;
+    s += rn * rn;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+pcg_update_p_kernel(double *__restrict__ p, const double *__restrict__ z, const double *__restrict__ sc,
+                    int64_t n) {
+  const double beta = sc[kBeta];
+  GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
+}
+
+// SplitMix64 counter stream (Steele, Lea, Flood 2014): value i of stream `key` is the
+// finalizer applied to key + (i+1) * 0x9E3779B97F4A7C15, mapped to [-1, 1).
+__global__ void __launch_bounds__(kBlock)
+random_start_kernel(double *__restrict__ v, int N1, uint64_t key) {
+  const int64_t n = int64_t(N1) * N1 * N1;
+  GRID_STRIDE(i, n) {
+    uint64_t z = key + uint64_t(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    const double u = 2.0 * double(z >> 11) * 0x1.0p-53 - 1.0;
+    const int x = int(i % N1), y = int((i / N1) % N1), zz = int(i / (int64_t(N1) * N1));
+    const bool bnd = on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(zz, N1);
+    v[i] = bnd ? 0.0 : u;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+jacobi_kernel(const double *__restrict__ dinv, const double *__restrict__ r, double *__restrict__ z,
+              int64_t n) {
+  GRID_STRIDE(i, n) z[i] = dinv[i] * r[i];
+}
+
+__global__ void __launch_bounds__(kBlock) zero_boundary_kernel(double *__restrict__ v, int N1) {
+  const int64_t n = int64_t(N1) * N1 * N1;
+  GRID_STRIDE(i, n) {
+    const int x = int(i % N1), y = int((i / N1) % N1), z = int(i / (int64_t(N1) * N1));
+    if (on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(z, N1)) v[i] = 0.0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill(void *dst, int dtype, int64_t n, double value, hipStream_t s) {
+  if (dtype == MFL_F64)
+    fill_kernel<double><<<grid_for(n), kBlock, 0, s>>>((double *)dst, n, value);
+  else
+    fill_kernel<float><<<grid_for(n), kBlock, 0, s>>>((float *)dst, n, float(value));
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(const void *src, int sd, void *dst, int dd, int64_t n, hipStream_t s) {
+  const int g = grid_for(n);
+  if (sd == MFL_F64 && dd == MFL_F32)
+    cast_kernel<double, float><<<g, kBlock, 0, s>>>((const double *)src, (float *)dst, n);
+  else if (sd == MFL_F32 && dd == MFL_F64)
+    cast_kernel<float, double><<<g, kBlock, 0, s>>>((const float *)src, (double *)dst, n);
+  else if (sd == MFL_F64)
+    cast_kernel<double, double><<<g, kBlock, 0, s>>>((const double *)src, (double *)dst, n);
+  else
+    cast_kernel<float, float><<<g, kBlock, 0, s>>>((const float *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen_kappa(const Level &coarse, const Level &fine, hipStream_t s) {
+  coarsen_kappa_kernel<<<grid_for(coarse.ncells), kBlock, 0, s>>>(fine.kappa64, coarse.kappa64,
+                                                                  coarse.kappa32, coarse.Nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_finalize(const Context &c, const Level &L, hipStream_t s) {
+  diag_finalize_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(L.diag64, L.dinv64, L.diag32, L.dinv32,
+                                                            L.N1, c.p.bc == MFL_BC_DIRICHLET);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_first(const void *b_in, int in_dtype, void *b_store, const void *dinv,
+                             void *d, void *x, int dtype, int64_t n, double inv_theta, hipStream_t s) {
+  const int g = grid_for(n);
+  if (dtype == MFL_F64) {
+    if (in_dtype != MFL_F64) return hipErrorInvalidValue;
+    cheb_first_kernel<double, double><<<g, kBlock, 0, s>>>((const double *)b_in, (double *)b_store,
+                                                           (const double *)dinv, (double *)d,
+                                                           (double *)x, n, inv_theta);
+  } else if (in_dtype == MFL_F64) {
+    cheb_first_kernel<double, float><<<g, kBlock, 0, s>>>((const double *)b_in, (float *)b_store,
+                                                          (const float *)dinv, (float *)d,
+                                                          (float *)x, n, float(inv_theta));
+  } else {
+    cheb_first_kernel<float, float><<<g, kBlock, 0, s>>>((const float *)b_in, (float *)b_store,
+                                                         (const float *)dinv, (float *)d, (float *)x,
+                                                         n, float(inv_theta));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_step(const void *b, const void *ax, const void *dinv, void *d, void *x,
+                            double *x64_out, int dtype, int64_t n, double c1, double c2,
+                            hipStream_t s) {
+  const int g = grid_for(n);
+  if (dtype == MFL_F64)
+    cheb_step_kernel<double><<<g, kBlock, 0, s>>>((const double *)b, (const double *)ax,
+                                                  (const double *)dinv, (double *)d, (double *)x,
+                                                  x64_out, n, c1, c2);
+  else
+    cheb_step_kernel<float><<<g, kBlock, 0, s>>>((const float *)b, (const float *)ax,
+                                                 (const float *)dinv, (float *)d, (float *)x, x64_out,
+                                                 n, float(c1), float(c2));
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t prolongate_k(const Context &c, const Level &coarse, const void *xc, int cd,
+                               void *xf, int fd, hipStream_t s) {
+  const int grid = int(coarse.ncells);
+  if (cd == MFL_F64 && fd == MFL_F64)
+    prolongate_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)xc, (double *)xf, coarse.Nc, c.transfer);
+  else if (cd == MFL_F64 && fd == MFL_F32)
+    prolongate_kernel<K, double, float><<<grid, kBlock, 0, s>>>((const double *)xc, (float *)xf, coarse.Nc, c.transfer);
+  else if (cd == MFL_F32 && fd == MFL_F32)
+    prolongate_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)xc, (float *)xf, coarse.Nc, c.transfer);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_prolongate_add(const Context &c, const Level &coarse, const Level &fine,
+                                 const void *xc, int cd, void *xf, int fd, hipStream_t s) {
+  (void)fine;
+#define CASE(K) return prolongate_k<K>(c, coarse, xc, cd, xf, fd, s)
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <int K>
+static hipError_t restrict_k(const Context &c, const Level &coarse, const void *bf, const void *axf,
+                             int fd, void *bc, int cd, hipStream_t s) {
+  const int grid = int(coarse.ncells);
+  if (fd == MFL_F64 && cd == MFL_F64)
+    restrict_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)bf, (const double *)axf, (double *)bc, coarse.Nc, c.transfer);
+  else if (fd == MFL_F32 && cd == MFL_F64)
+    restrict_kernel<K, float, double><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (double *)bc, coarse.Nc, c.transfer);
+  else if (fd == MFL_F32 && cd == MFL_F32)
+    restrict_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (float *)bc, coarse.Nc, c.transfer);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_residual(const Context &c, const Level &coarse, const Level &fine,
+                                    const void *bf, const void *axf, int fd, void *bc, int cd,
+                                    hipStream_t s) {
+  (void)fine;
+  hipError_t e = launch_fill(bc, cd, coarse.ndofs, 0.0, s);
+  if (e != hipSuccess) return e;
+#define CASE(K) return restrict_k<K>(c, coarse, bf, axf, fd, bc, cd, s)
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dot_partial(const double *a, const double *b, int64_t n, double *partials,
+                              hipStream_t s) {
+  dot_partial_kernel<<<kReduceBlocks, kBlock, 0, s>>>(a, b, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, double *scalars, int which, int op, hipStream_t s) {
+  finalize_kernel<<<1, kBlock, 0, s>>>(partials, scalars, which, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update_xr(double *x, double *r, const double *p, const double *q,
+                                const double *scalars, int64_t n, double *partials, hipStream_t s) {
+  pcg_update_xr_kernel<<<kReduceBlocks, kBlock, 0, s>>>(x, r, p, q, scalars, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update_p(double *p, const double *z, const double *scalars, int64_t n,
+                               hipStream_t s) {
+  pcg_update_p_kernel<<<grid_for(n), kBlock, 0, s>>>(p, z, scalars, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_random_start(double *v, const Level &L, uint64_t key, hipStream_t s) {
+  random_start_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const double *dinv, const double *r, double *z, int64_t n, hipStream_t s) {
+  jacobi_kernel<<<grid_for(n), kBlock, 0, s>>>(dinv, r, z, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_boundary(double *v, const Level &L, hipStream_t s) {
+  zero_boundary_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1);
+  return hipGetLastError();
+}
+
+}  // namespace mfl

@@ -1,0 +1,134 @@
+// Internal declarations of the matrix-free Laplace library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mfl.h"
+
+namespace mfl {
+
+constexpr int kMaxDegree = 8;
+constexpr int kMaxN = kMaxDegree + 1;
+constexpr int kMaxM = 2 * kMaxDegree + 1;   // fine points per coarse cell and direction
+constexpr int kReduceBlocks = 1024;         // partial sums of the vector reductions
+
+// One-dimensional tables of degree k (n = k+1 entries per direction), passed to the
+// kernels by value so that fully unrolled loops read them through scalar loads.
+//   S [q n + i] : GLL-Lagrange basis i at Gauss point q
+//   Sd[q n + i] : derivative of GLL-Lagrange basis i at Gauss point q
+//   D [q n + p] : derivative of Gauss-Lagrange basis p at Gauss point q (collocation)
+//   M, K        : reference [0,1] mass and stiffness matrices of the GLL basis
+//   Fv, Fd      : Gauss-Lagrange basis p and its derivative at xi = 0 (p) and xi = 1 (n + p)
+//   w, gll      : Gauss weights, GLL nodes on [0,1]
+template <int N, typename T>
+struct Tab {
+  T S[N * N];
+  T Sd[N * N];
+  T D[N * N];
+  T M[N * N];
+  T K[N * N];
+  T Fv[2 * N];
+  T Fd[2 * N];
+  T w[N];
+  T gll[N];
+};
+
+// Embedding of the coarse GLL basis in the fine grid lines of one coarse cell:
+// P[f (k+1) + i] = coarse basis i at the f-th of the 2k+1 fine points.
+struct TransferTab {
+  double P[kMaxM * kMaxN];
+};
+
+struct Level {
+  int Nc = 0;           // cells per direction
+  int N1 = 0;           // CG grid lines per direction (k Nc + 1)
+  int64_t ncells = 0;
+  int64_t ndofs = 0;
+  double h = 0.0;
+  double *kappa64 = nullptr;
+  float *kappa32 = nullptr;
+  double *metric64 = nullptr;   // curved: [cell][6][n^3], w_q det J J^{-1} J^{-T}
+  float *metric32 = nullptr;
+  double *diag64 = nullptr;
+  double *dinv64 = nullptr;
+  float *diag32 = nullptr;
+  float *dinv32 = nullptr;
+  // multigrid vectors in the cycle's precision (FP64 on the coarsest level)
+  void *b = nullptr, *x = nullptr, *ax = nullptr, *d = nullptr;
+  bool mg_f32 = false;          // vectors of this level are float
+  double lambda_max = 0.0;
+  double coarse_lmin = 0.0, coarse_lmax = 0.0;
+  int coarse_steps = 0;
+};
+
+struct Context {
+  mfl_params p{};
+  int k = 0, n = 0;
+  std::vector<Level> levels;
+  Tab<kMaxN, double> tab64{};
+  Tab<kMaxN, float> tab32{};
+  TransferTab transfer{};
+  // FP64 work vectors of the finest level (PCG and eigenvalue estimates)
+  double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
+  double *partials = nullptr;   // kReduceBlocks doubles
+  double *scalars = nullptr;    // device scalars (see enum Scalar)
+  double *host_scalars = nullptr;   // pinned host mirror
+};
+
+enum Scalar { kRZ = 0, kPQ, kAlpha, kBeta, kRR, kBB, kRZnew, kNumScalars = 16 };
+
+// ---- host-side tables -------------------------------------------------------
+void gauss_legendre(int n, double *x, double *w);
+void gauss_lobatto(int n, double *x, double *w);
+void lagrange_eval(int n, const double *nodes, double x, double *val, double *der);
+void build_tables(int k, Tab<kMaxN, double> &t64, Tab<kMaxN, float> &t32, TransferTab &tt);
+
+// ---- kernel launchers (return hipError_t of the launch) -----------------------
+hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
+                                void *dst, hipStream_t s);
+hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
+                           hipStream_t s);
+hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *u, const double *lam,
+                                double *grad, hipStream_t s);
+hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s);
+hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s);
+hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStream_t s);
+hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
+                             hipStream_t s);
+
+// multigrid and vector kernels
+hipError_t launch_fill(void *dst, int dtype, int64_t n, double value, hipStream_t s);
+hipError_t launch_cast(const void *src, int src_dtype, void *dst, int dst_dtype, int64_t n,
+                       hipStream_t s);
+hipError_t launch_coarsen_kappa(const Level &coarse, const Level &fine, hipStream_t s);
+hipError_t launch_diag_finalize(const Context &c, const Level &L, hipStream_t s);
+hipError_t launch_cheb_first(const void *b_in, int in_dtype, void *b_store, const void *dinv,
+                             void *d, void *x, int dtype, int64_t n, double inv_theta, hipStream_t s);
+hipError_t launch_cheb_step(const void *b, const void *ax, const void *dinv, void *d, void *x,
+                            double *x64_out, int dtype, int64_t n, double c1, double c2,
+                            hipStream_t s);
+hipError_t launch_prolongate_add(const Context &c, const Level &coarse, const Level &fine,
+                                 const void *xc, int c_dtype, void *xf, int f_dtype, hipStream_t s);
+hipError_t launch_restrict_residual(const Context &c, const Level &coarse, const Level &fine,
+                                    const void *bf, const void *axf, int f_dtype, void *bc,
+                                    int c_dtype, hipStream_t s);
+hipError_t launch_dot_partial(const double *a, const double *b, int64_t n, double *partials,
+                              hipStream_t s);
+hipError_t launch_finalize(const double *partials, double *scalars, int which, int op,
+                           hipStream_t s);
+hipError_t launch_pcg_update_xr(double *x, double *r, const double *p, const double *q,
+                                const double *scalars, int64_t n, double *partials, hipStream_t s);
+hipError_t launch_pcg_update_p(double *p, const double *z, const double *scalars, int64_t n,
+                               hipStream_t s);
+hipError_t launch_random_start(double *v, const Level &L, uint64_t key, hipStream_t s);
+hipError_t launch_jacobi(const double *dinv, const double *r, double *z, int64_t n, hipStream_t s);
+hipError_t launch_zero_boundary(double *v, const Level &L, hipStream_t s);
+
+// finalize ops
+enum FinalizeOp { kFinSum = 0, kFinAlpha = 1, kFinBeta = 2 };
+
+}  // namespace mfl

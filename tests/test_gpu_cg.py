@@ -1,0 +1,198 @@
+"""GPU parity of the continuous Q_k path against the CPU oracle (through the C ABI).
+
+Tolerances: FP64 operator results within 1e-12 relative (max norm) of the oracle;
+FP32 results within 1e-5; solver outputs within 1e-8 of the oracle's solution.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1611_03029_amd as mfl
+from oracle import adjoint as o_adj
+from oracle import cg as o_cg
+from oracle import mg as o_mg
+from oracle.mesh import Box
+from seeded_inputs import (SEED_CG_Q2_SMALL, SEED_CG_Q4_CURVED, SEED_KAPPA_FIELD, choose_cells,
+                           gaussian_field, uniform_vector)
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def rel_err(a, b):
+    a = a.detach().cpu().numpy() if torch.is_tensor(a) else a
+    b = b.detach().cpu().numpy() if torch.is_tensor(b) else b
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def t(x, dtype=torch.float64):
+    return torch.as_tensor(np.asarray(x), dtype=dtype, device=DEV)
+
+
+def kappa_field(n, seed=SEED_KAPPA_FIELD):
+    return np.exp(gaussian_field(n, seed, 0.5))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("geom", ["cartesian", "curved"])
+def test_apply_fp64_matches_csr(k, geom):
+    Nc = 4 if k <= 4 else 3
+    a = 0.1 if geom == "curved" else 0.0
+    box = Box(Nc, k, a)
+    kap = kappa_field(box.n_cells)
+    prob = mfl.Problem(k, Nc, kappa=kap, geometry=mfl.CURVED if a else mfl.CARTESIAN, curve_amp=0.1)
+    u = uniform_vector(box.n_dofs, SEED_CG_Q2_SMALL + k)
+    y = prob.apply(t(u))
+    ref = o_cg.assemble(box, kap) @ u
+    assert rel_err(y, ref) <= 1e-12
+    # FP32 variant against the FP64 oracle
+    y32 = prob.apply(t(u, torch.float32))
+    assert rel_err(y32.double(), ref) <= 2e-5
+
+
+@pytest.mark.parametrize("geom", [0.0, 0.1])
+def test_neumann_apply_and_null_space(geom):
+    k, Nc = 3, 3
+    box = Box(Nc, k, geom)
+    prob = mfl.Problem(k, Nc, geometry=mfl.CURVED if geom else mfl.CARTESIAN, bc=mfl.NEUMANN)
+    u = uniform_vector(box.n_dofs, 5)
+    assert rel_err(prob.apply(t(u)), o_cg.assemble(box, bc="neumann") @ u) <= 1e-12
+    ones = torch.ones(box.n_dofs, dtype=torch.float64, device=DEV)
+    assert prob.apply(ones).abs().max().item() <= 1e-12
+
+
+def test_cg_q2_small_config_apply():
+    """CG Q2, 8^3 affine cells (17^3 DoFs), seeded U[-1,1] input."""
+    box = Box(8, 2)
+    prob = mfl.Problem(2, 8)
+    u = uniform_vector(box.n_dofs, SEED_CG_Q2_SMALL)
+    assert prob.n_dofs == 17 ** 3
+    assert rel_err(prob.apply(t(u)), o_cg.assemble(box) @ u) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_cg_q4_curved_full_size_sampled_rows(dtype):
+    """CG Q4 on 64^3 curved cells (257^3 DoFs): oracle rows computed one by one."""
+    box = Box(64, 4, 0.1)
+    prob = mfl.Problem(4, 64, geometry=mfl.CURVED, curve_amp=0.1)
+    u = uniform_vector(box.n_dofs, SEED_CG_Q4_CURVED)
+    y = prob.apply(t(u, dtype)).double().cpu().numpy()
+    rows = np.random.default_rng(21).choice(box.n_dofs, 150, replace=False)
+    rows[:4] = [0, 257 * 257 + 258, box.n_dofs // 2, box.n_dofs - 259]
+    ref = o_cg.apply_rows(box, u, rows)
+    scale = np.abs(ref).max()
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert np.abs(y[rows] - ref).max() <= tol * scale
+    assert np.isfinite(y).all()
+
+
+def test_apply_is_deterministic_to_rounding():
+    prob = mfl.Problem(3, 8, geometry=mfl.CURVED)
+    u = t(uniform_vector(prob.n_dofs, 9))
+    y1, y2 = prob.apply(u), prob.apply(u)
+    assert rel_err(y1, y2) <= 1e-14
+
+
+@pytest.mark.parametrize("geom", [0.0, 0.1])
+def test_diagonal_matches_oracle(geom):
+    k, Nc = 3, 4
+    box = Box(Nc, k, geom)
+    kap = kappa_field(box.n_cells)
+    prob = mfl.Problem(k, Nc, kappa=kap, geometry=mfl.CURVED if geom else mfl.CARTESIAN)
+    d = prob.diagonal()
+    assert rel_err(d, o_cg.assemble(box, kap).diagonal()) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_rhs_sine_matches_oracle(k):
+    for a in (0.0, 0.1):
+        box = Box(4, k, a)
+        prob = mfl.Problem(k, 4, geometry=mfl.CURVED if a else mfl.CARTESIAN)
+        assert rel_err(prob.rhs_sine(), o_cg.rhs(box)) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_transfer_matches_oracle_embedding(k):
+    prob = mfl.Problem(k, 8, build_mg=True, min_level_cells=2)
+    lev = prob.num_levels - 1
+    fine, coarse = Box(8, k), Box(4, k)
+    P = o_mg.prolongation(coarse, fine)
+    uc = uniform_vector(coarse.n_dofs, 11)
+    uf = uniform_vector(fine.n_dofs, 12)
+    out = t(uf.copy())
+    prob.transfer(lev, 0, t(uc), out)
+    assert rel_err(out, uf + P @ uc) <= 1e-13
+    rc = torch.empty(coarse.n_dofs, dtype=torch.float64, device=DEV)
+    prob.transfer(lev, 1, t(uf), rc)
+    assert rel_err(rc, P.T @ uf) <= 1e-13
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_eigenvalue_estimates_match_oracle(k):
+    prob = mfl.Problem(k, 8, build_mg=True)
+    ref = o_mg.Multigrid(8, k)
+    for l, lev in enumerate(ref.levels):
+        info = prob.level_info(l)
+        if l == 0:
+            assert abs(info["coarse_lmin"] - lev["lmin"]) <= 1e-8 * lev["lmax"]
+            assert abs(info["coarse_lmax"] - lev["lmax"]) <= 1e-8 * lev["lmax"]
+            assert info["coarse_steps"] == lev["steps"]
+        else:
+            assert abs(info["lambda_max"] - lev["lambda"]) <= 1e-10 * lev["lambda"]
+
+
+def test_vcycle_fp64_matches_oracle():
+    k, Nc = 2, 8
+    prob = mfl.Problem(k, Nc, build_mg=True)
+    ref = o_mg.Multigrid(Nc, k)
+    r = uniform_vector(prob.n_dofs, 13)
+    r[ref.levels[-1]["box"].boundary_mask()] = 0.0
+    z = prob.vcycle(t(r))
+    assert rel_err(z, ref.vcycle(r)) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [mfl.F64, mfl.F32])
+@pytest.mark.parametrize("k", [2, 3])
+def test_pcg_solve_matches_oracle(prec, k):
+    Nc = 8
+    prob = mfl.Problem(k, Nc, build_mg=True, mg_precision=prec)
+    b = prob.rhs_sine()
+    x, its, res = prob.solve(b, rtol=1e-10, maxit=50)
+    out = o_mg.solve(Nc, k, tol=1e-10)
+    assert res <= 1e-10
+    assert rel_err(x, out["x"]) <= 1e-8
+    if prec == mfl.F64:
+        assert its == out["iterations"]
+    else:
+        assert its <= out["iterations"] + 2
+    # the discretization error is the oracle's
+    assert abs(o_cg.l2_error(Box(Nc, k), x.cpu().numpy()) - o_cg.l2_error(Box(Nc, k), out["x"])) <= 1e-9
+
+
+def test_pcg_error_paths():
+    prob = mfl.Problem(2, 8, build_mg=True)
+    b = prob.rhs_sine()
+    x, its, res = prob.solve(b, rtol=1e-14, maxit=1, raise_on_noconv=False)
+    assert its == 1 and res > 1e-14
+    with pytest.raises(mfl.MflError) as e:
+        prob.solve(b, rtol=1e-14, maxit=1)
+    assert e.value.code == mfl._mfl.MFL_ENOCONV
+    bn = b.clone()
+    bn[100] = float("nan")
+    with pytest.raises(mfl.MflError) as e:
+        prob.solve(bn)
+    assert e.value.code == mfl._mfl.MFL_EBREAKDOWN
+    z = torch.zeros_like(b)
+    x, its, res = prob.solve(z)
+    assert its == 0 and x.abs().max().item() == 0.0
+
+
+def test_kappa_gradient_matches_oracle():
+    k, Nc = 2, 4
+    box = Box(Nc, k)
+    kap = kappa_field(box.n_cells)
+    prob = mfl.Problem(k, Nc, kappa=kap, build_mg=True)
+    u = uniform_vector(box.n_dofs, 31)
+    lam = uniform_vector(box.n_dofs, 32)
+    g = prob.kappa_gradient(t(u), t(lam))
+    assert rel_err(g, o_adj.gradient(box, u, lam)) <= 1e-12
