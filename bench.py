@@ -1,0 +1,187 @@
+"""Benchmark of the matrix-free Laplace hot path on one MI355X.
+
+Timed step: one FP64 operator application dst = A src of the continuous Q4 Laplacian
+on 64^3 curved cells (257^3 = 16,974,593 DoFs; deformation x + 0.1 sin(pi x) sin(pi y)
+sin(pi z) per coordinate; 5 Gauss points per direction; seeded U[-1,1] input already in
+HBM).  value = DoFs / second of that step.
+
+Also reported (outside the timed region):
+  * the dominant kernel (the curved-cell operator kernel) timed with HIP events on its
+    stream, against the HBM roofline with the algorithmic bytes of one application;
+  * the FP32 application of the same operator;
+  * GMG-PCG time to solution with the V-cycle in FP32 and in FP64 inside the FP64
+    outer CG (Cartesian 64^3 fine level, levels down to 2^3, Chebyshev(5)-Jacobi,
+    tolerance 1e-10 relative residual, sine right-hand side);
+  * the CPU oracle (element-by-element dense element matrices) timed on the host for a
+    bounded sample of rows of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve-degrees 2,4]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "matrix-free Laplace apply DoFs/s (FP64) + GMG-PCG time-to-solution FP32-MG vs FP64"
+
+
+def apply_bytes(n_dofs, n_cells, q_per_cell, real_bytes, curved=True):
+    """Algorithmic bytes of one application: read src, write dst once, stream the
+    6-entry metric per quadrature point and one kappa per cell."""
+    b = 2 * real_bytes * n_dofs + real_bytes * n_cells
+    if curved:
+        b += 6 * real_bytes * q_per_cell * n_cells
+    return b
+
+
+def time_applies(prob, src, dst, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        prob.apply(src, dst)
+    torch.cuda.synchronize()
+    prob.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.apply(src, dst)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kern_ms = prob.profile_stop()
+    return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches
+
+
+def solve_comparison(degree, cells, repeats=2):
+    import torch
+    import paper_1611_03029_amd as mfl
+    out = {}
+    xs = {}
+    for name, prec in (("fp64_mg", mfl.F64), ("fp32_mg", mfl.F32)):
+        t0 = time.perf_counter()
+        prob = mfl.Problem(degree, cells, build_mg=True, mg_precision=prec)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        b = prob.rhs_sine()
+        best = None
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, its, res = prob.solve(b, rtol=1e-10, maxit=100)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        xs[name] = x
+        out[name] = {"time_s": best, "iterations": its, "final_rel_residual": res,
+                     "setup_s": setup_s, "dofs_per_s": prob.n_dofs / best}
+        del prob
+    diff = (xs["fp32_mg"] - xs["fp64_mg"]).abs().max().item() / xs["fp64_mg"].abs().max().item()
+    out["n_dofs"] = int(xs["fp64_mg"].numel())
+    out["speedup_fp32_mg"] = out["fp64_mg"]["time_s"] / out["fp32_mg"]["time_s"]
+    out["max_rel_diff_fp32_vs_fp64_solution"] = diff
+    return out
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle's element-by-element apply (dense element matrices from per-point
+    integrals) on sampled rows of the 64^3 curved Q4 workload, one host thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cg as o_cg
+    from oracle.mesh import Box
+    from seeded_inputs import SEED_CG_Q4_CURVED, uniform_vector
+
+    box = Box(64, 4, 0.1)
+    u = uniform_vector(box.n_dofs, SEED_CG_Q4_CURVED)
+    rng = np.random.default_rng(99)
+    done, t_used = 0, 0.0
+    with threadpool_limits(1):
+        while t_used < budget_s:
+            rows = rng.choice(box.n_dofs, 64, replace=False)
+            t0 = time.perf_counter()
+            o_cg.apply_rows(box, u, rows)
+            t_used += time.perf_counter() - t0
+            done += len(rows)
+    return {"value": done / t_used, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
+            "sample": "%d sampled rows of CG Q4 64^3 curved (dense element matrices per "
+                      "cell, element-by-element), %.1f s on 1 host thread" % (done, t_used)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--solve-degrees", default="2,4")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path is single-GPU (multi-GPU sharding is a "
+              "design note, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1611_03029_amd as mfl
+    from seeded_inputs import SEED_CG_Q4_CURVED, uniform_vector
+
+    torch.cuda.set_device(0)
+    k, Nc = 4, 64
+    prob = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1)
+    n, cells, q = prob.n_dofs, prob.n_cells, (k + 1) ** 3
+    u64 = torch.tensor(uniform_vector(n, SEED_CG_Q4_CURVED), dtype=torch.float64, device="cuda")
+    y64 = torch.empty_like(u64)
+    ms_step, kern_ms, launches = time_applies(prob, u64, y64, args.steps, args.warmup)
+    bytes64 = apply_bytes(n, cells, q, 8)
+    achieved = bytes64 / (kern_ms * 1e-3) / 1e9
+
+    u32 = u64.float()
+    y32 = torch.empty_like(u32)
+    ms32, kern32, _ = time_applies(prob, u32, y32, max(args.steps // 2, 10), args.warmup)
+    bytes32 = apply_bytes(n, cells, q, 4)
+    del prob, u64, y64, u32, y32
+    torch.cuda.empty_cache()
+
+    solves = {}
+    for d in [int(s) for s in args.solve_degrees.split(",") if s.strip()]:
+        solves["Q%d_64^3" % d] = solve_comparison(d, 64)
+        torch.cuda.empty_cache()
+
+    result = {
+        "metric": METRIC,
+        "value": n / (ms_step * 1e-3),
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "CG Q4 operator apply, 64^3 curved cells (257^3 DoFs), FP64",
+                   "degree": k, "cells_per_dim": Nc, "n_dofs": n, "geometry": "x+0.1 sin sin sin",
+                   "quadrature": "Gauss %d^3" % (k + 1), "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "curved_kernel<4,double>", "kernel_ms": kern_ms,
+                     "algorithmic_bytes": bytes64, "timed_launches": launches},
+        "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32,
+                       "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
+                       "frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "gmg_pcg": solves,
+        "paper_context": {"cg_curved_q4_dofs_per_s": 4.58e8,
+                          "hardware": "2x14-core Xeon E5-2690 v4 (Broadwell), FP64, 393216-cell shell"},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,13 @@ int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double r
 int mfl_kappa_gradient(mfl_handle h, const double *u, const double *lambda, double *grad,
                        void *stream);
 
+/* Timing of the operator's cell kernel (the dominant kernel of mfl_apply): enable = 1 starts
+ * recording a HIP event pair around every cell-kernel launch that mfl_apply enqueues (on the
+ * caller's stream, up to 8192 launches); enable = 0 stops, synchronizes on the recorded events
+ * and returns the number of timed launches and their summed duration in milliseconds.
+ * Outputs may be NULL. */
+int mfl_profile(mfl_handle h, int enable, int *launches, double *total_ms);
+
 /* Release the handle (the workspace stays owned by the caller). */
 int mfl_destroy(mfl_handle h);
 

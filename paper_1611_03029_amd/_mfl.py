@@ -65,6 +65,7 @@ SIGNATURES = {
     "mfl_rhs_sine": (ctypes.c_int, [P, P, P]),
     "mfl_adjoint_solve": (ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_int, IP, DP, P]),
     "mfl_kappa_gradient": (ctypes.c_int, [P, P, P, P, P]),
+    "mfl_profile": (ctypes.c_int, [P, ctypes.c_int, IP, DP]),
     "mfl_destroy": (ctypes.c_int, [P]),
     "mfl_last_error": (ctypes.c_char_p, []),
 }
@@ -158,6 +159,12 @@ class Problem:
     def num_levels(self):
         return _check(lib().mfl_num_levels(self.handle), allow=range(1, 1 << 20))
 
+    def _level_dofs(self, level):
+        cache = self.__dict__.setdefault("_dofs_cache", {})
+        if level not in cache:
+            cache[level] = self.level_info(level)["n_dofs"]
+        return cache[level]
+
     def level_info(self, level=-1):
         c, nd = ctypes.c_int(), ctypes.c_int64()
         lam, lmin, lmax, st = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
@@ -165,6 +172,16 @@ class Problem:
                                     ctypes.byref(lmin), ctypes.byref(lmax), ctypes.byref(st)))
         return {"cells_per_dim": c.value, "n_dofs": nd.value, "lambda_max": lam.value,
                 "coarse_lmin": lmin.value, "coarse_lmax": lmax.value, "coarse_steps": st.value}
+
+    def profile_start(self):
+        """Start timing the operator cell kernels launched by apply() with HIP events."""
+        _check(lib().mfl_profile(self.handle, 1, None, None))
+
+    def profile_stop(self):
+        """Stop timing; returns (number of timed cell-kernel launches, total ms)."""
+        n, ms = ctypes.c_int(), ctypes.c_double()
+        _check(lib().mfl_profile(self.handle, 0, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def set_kappa(self, kappa):
         self._kappa = self._as_f64(kappa, self.n_cells)
@@ -174,7 +191,7 @@ class Problem:
         dtype = F32 if src.dtype == torch.float32 else F64
         if src.dtype != _DT[dtype] or not src.is_contiguous() or src.device.type != "cuda":
             raise ValueError("src must be a contiguous float64/float32 CUDA tensor")
-        n = self.level_info(level)["n_dofs"]
+        n = self._level_dofs(level)
         if src.numel() != n:
             raise ValueError("src has %d values, level has %d DoFs" % (src.numel(), n))
         if dst is None:

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmfl.so")
-SOURCES = ["tables", "kernels_cg", "kernels_mg", "kernels_sipg", "api"]
+SOURCES = ["tables", "kernels_cg", "kernels_setup", "kernels_mg", "kernels_sipg", "api"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -113,6 +113,7 @@ int64_t layout(Context &c, char *base) {
       L.metric32 = b.take<float>(L.ncells * 6 * n3);
     }
     if (cg) {
+      L.halo = b.take<double>(cg_halo_elements(c.k, L.Nc));
       L.diag64 = b.take<double>(L.ndofs);
       L.dinv64 = b.take<double>(L.ndofs);
       L.diag32 = b.take<float>(L.ndofs);
@@ -195,13 +196,27 @@ void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b
   lmax = bisect(m - 1);
 }
 
-int apply_level(Context &c, int l, int dtype, const void *src, void *dst, hipStream_t s) {
+constexpr int kMaxProfiled = 8192;
+
+int apply_level(Context &c, int l, int dtype, const void *src, void *dst, hipStream_t s,
+                bool timed = false) {
   const Level &L = c.levels[l];
+  const bool rec = timed && c.profiling && c.prof_used < kMaxProfiled;
+  if (rec && c.prof_used == int(c.prof_start.size())) {
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    c.prof_start.push_back(a);
+    c.prof_stop.push_back(b);
+  }
+  if (rec) HIP_TRY(hipEventRecord(c.prof_start[c.prof_used], s));
   if (c.p.disc == MFL_DISC_SIPG) {
     HIP_TRY(launch_sipg_apply(c, L, dtype, src, dst, s));
   } else {
     HIP_TRY(launch_cg_apply(c, L, dtype, src, dst, s));
   }
+  if (rec) HIP_TRY(hipEventRecord(c.prof_stop[c.prof_used++], s));
+  if (c.p.disc == MFL_DISC_CG) HIP_TRY(launch_cg_halo_add(c, L, dtype, dst, s));
   return MFL_OK;
 }
 
@@ -518,7 +533,30 @@ int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, vo
   if (dtype != MFL_F64 && dtype != MFL_F32) return fail(MFL_EINVAL, "unknown dtype %d", dtype);
   if (!src || !dst) return fail(MFL_EINVAL, "src/dst is NULL");
   if (src == dst) return fail(MFL_EINVAL, "src and dst must not overlap");
-  return apply_level(*h, l, dtype, src, dst, as_stream(stream));
+  return apply_level(*h, l, dtype, src, dst, as_stream(stream), true);
+}
+
+int mfl_profile(mfl_handle h, int enable, int *launches, double *total_ms) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (launches) *launches = 0;
+  if (total_ms) *total_ms = 0.0;
+  if (enable) {
+    h->profiling = true;
+    h->prof_used = 0;
+    return MFL_OK;
+  }
+  double sum = 0.0;
+  for (int i = 0; i < h->prof_used; ++i) {
+    HIP_TRY(hipEventSynchronize(h->prof_stop[i]));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->prof_start[i], h->prof_stop[i]));
+    sum += ms;
+  }
+  if (launches) *launches = h->prof_used;
+  if (total_ms) *total_ms = sum;
+  h->profiling = false;
+  h->prof_used = 0;
+  return MFL_OK;
 }
 
 int mfl_diagonal(mfl_handle h, int level, int dtype, void *out, void *stream) {
@@ -611,6 +649,8 @@ int mfl_kappa_gradient(mfl_handle h, const double *u, const double *lambda, doub
 int mfl_destroy(mfl_handle h) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
   if (h->host_scalars) (void)hipHostFree(h->host_scalars);
+  for (hipEvent_t e : h->prof_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->prof_stop) (void)hipEventDestroy(e);
   delete h;
   return MFL_OK;
 }

@@ -1,0 +1,166 @@
+// Compile-time one-dimensional rules and even-odd matrices for the operator kernels.
+//
+// The kernels apply four 1D matrices along every line of a cell (Sec. 3: sum
+// factorization; Sec. 2.1: GLL-Lagrange basis; k+1 Gauss points):
+//   M, K : reference [0,1] mass and stiffness of the GLL basis (exact Gauss integrals),
+//   S    : GLL basis at the Gauss points,
+//   D    : collocation derivative of the Gauss-point Lagrange basis at the Gauss points.
+// Computing them here as constexpr values makes every coefficient an immediate in the
+// instruction stream, so the compiler rematerializes coefficients instead of holding them
+// in scalar registers for the whole kernel.  The host library computes the same rules
+// (tables.hip) for the setup kernels and for the oracle-independent consistency check.
+#pragma once
+
+#include "mfl_internal.h"
+
+namespace mfl {
+namespace ct {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// cos by its Taylor series (|x| <= pi: 40 terms are far past double precision)
+constexpr double cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double abs_(double x) { return x < 0 ? -x : x; }
+
+// Legendre P_m(x) and P_m'(x)
+struct LegVal {
+  double P, dP;
+};
+constexpr LegVal legendre(int m, double x) {
+  if (m == 0) return {1.0, 0.0};
+  double p0 = 1.0, p1 = x;
+  for (int j = 2; j <= m; ++j) {
+    const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  return {p1, m * (x * p1 - p0) / (x * x - 1.0)};
+}
+
+template <int N>
+struct Rules {
+  double xg[N], wg[N];   // Gauss-Legendre on [0,1]
+  double xl[N];          // Gauss-Lobatto-Legendre on [0,1]
+};
+
+template <int N>
+constexpr Rules<N> rules() {
+  Rules<N> r{};
+  for (int j = 0; j < N; ++j) {   // Gauss: Newton on P_N
+    double t = -cos_series(kPi * (j + 0.75) / (N + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      const LegVal v = legendre(N, t);
+      const double dt = v.P / v.dP;
+      t -= dt;
+      if (abs_(dt) < 1e-17) break;
+    }
+    const LegVal v = legendre(N, t);
+    r.xg[j] = 0.5 * (t + 1.0);
+    r.wg[j] = 1.0 / ((1.0 - t * t) * v.dP * v.dP);
+  }
+  const int k = N - 1;
+  for (int j = 0; j < N; ++j) {   // Gauss-Lobatto: end points and roots of P_k'
+    double t = j == 0 ? -1.0 : (j == k ? 1.0 : -cos_series(kPi * j / k));
+    if (j > 0 && j < k) {
+      for (int it = 0; it < 100; ++it) {
+        const LegVal v = legendre(k, t);
+        const double d2P = (2.0 * t * v.dP - k * (k + 1.0) * v.P) / (1.0 - t * t);
+        const double dt = v.dP / d2P;
+        t -= dt;
+        if (abs_(dt) < 1e-17) break;
+      }
+    }
+    r.xl[j] = 0.5 * (t + 1.0);
+  }
+  return r;
+}
+
+// value and derivative of the Lagrange polynomial i of `nodes` at x
+template <int N>
+constexpr LegVal lagrange(const double (&nodes)[N], int i, double x) {
+  double v = 1.0;
+  for (int j = 0; j < N; ++j)
+    if (j != i) v *= (x - nodes[j]) / (nodes[i] - nodes[j]);
+  double d = 0.0;
+  for (int m = 0; m < N; ++m) {
+    if (m == i) continue;
+    double t = 1.0 / (nodes[i] - nodes[m]);
+    for (int j = 0; j < N; ++j)
+      if (j != i && j != m) t *= (x - nodes[j]) / (nodes[i] - nodes[j]);
+    d += t;
+  }
+  return {v, d};
+}
+
+template <int N>
+struct Dense {
+  double M[N * N], K[N * N], S[N * N], D[N * N];
+};
+
+template <int N>
+constexpr Dense<N> dense() {
+  const Rules<N> r = rules<N>();
+  Dense<N> o{};
+  double S[N * N] = {}, Sd[N * N] = {};
+  for (int q = 0; q < N; ++q)
+    for (int i = 0; i < N; ++i) {
+      const LegVal v = lagrange<N>(r.xl, i, r.xg[q]);
+      S[q * N + i] = v.P;
+      Sd[q * N + i] = v.dP;
+      o.D[q * N + i] = lagrange<N>(r.xg, i, r.xg[q]).dP;
+    }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double m = 0.0, s = 0.0;
+      for (int q = 0; q < N; ++q) {
+        m += r.wg[q] * S[q * N + i] * S[q * N + j];
+        s += r.wg[q] * Sd[q * N + i] * Sd[q * N + j];
+      }
+      o.M[i * N + j] = m;
+      o.K[i * N + j] = s;
+    }
+  for (int i = 0; i < N * N; ++i) o.S[i] = S[i];
+  return o;
+}
+
+template <int N, typename T>
+constexpr EO<N, T> to_eo(const double (&A)[N * N]) {
+  EO<N, T> e{};
+  constexpr int H = N / 2;
+  for (int q = 0; q < H; ++q) {
+    for (int i = 0; i < H; ++i) {
+      e.ep[q * H + i] = T(0.5 * (A[q * N + i] + A[q * N + N - 1 - i]));
+      e.op[q * H + i] = T(0.5 * (A[q * N + i] - A[q * N + N - 1 - i]));
+    }
+    e.ec[q] = (N % 2) ? T(A[q * N + H]) : T(0);
+  }
+  for (int i = 0; i <= H; ++i) e.mid[i] = (N % 2) ? T(A[H * N + i]) : T(0);
+  return e;
+}
+
+template <int N, typename T>
+constexpr EOTab<N, T> eotab() {
+  const Dense<N> d = dense<N>();
+  EOTab<N, T> e{};
+  e.M = to_eo<N, T>(d.M);
+  e.K = to_eo<N, T>(d.K);
+  e.S = to_eo<N, T>(d.S);
+  e.D = to_eo<N, T>(d.D);
+  return e;
+}
+
+template <int N, typename T>
+struct Tables {
+  static constexpr EOTab<N, T> eo = eotab<N, T>();
+};
+
+}  // namespace ct
+}  // namespace mfl

@@ -20,6 +20,12 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk) {
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 
+// LDS atomic add without return (ds_add_f64 / ds_add_f32)
+template <typename T>
+__device__ __forceinline__ void lds_add(T *p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ bool on_boundary(int g, int N1) { return g == 0 || g == N1 - 1; }
 
 // Copy of the first N*N entries of the kMaxN-sized host tables (rows of length N).
@@ -42,6 +48,86 @@ Tab<N, T> shrink_tab(const Tab<kMaxN, T> &t) {
     o.gll[i] = t.gll[i];
   }
   return o;
+}
+
+template <int N, typename T>
+EOTab<N, T> make_eotab(const Tab<kMaxN, T> &t) {
+  // the dense tables have rows of length N; rebuild them in double for the even-odd split
+  double M[N * N], K[N * N], S[N * N], D[N * N];
+  for (int i = 0; i < N * N; ++i) {
+    M[i] = double(t.M[i]);
+    K[i] = double(t.K[i]);
+    S[i] = double(t.S[i]);
+    D[i] = double(t.D[i]);
+  }
+  EOTab<N, T> e;
+  e.M = make_eo<N, T>(M);
+  e.K = make_eo<N, T>(K);
+  e.S = make_eo<N, T>(S);
+  e.D = make_eo<N, T>(D);
+  return e;
+}
+
+// out = A u with A in even-odd form; SG = +1 (centro-symmetric) or -1 (antisymmetric).
+// N^2/2 + O(N) multiply-adds instead of N^2.
+template <int N, int SG, typename T>
+__host__ __device__ __forceinline__ void eo_apply(const EO<N, T> &a, const T *u, T *out) {
+  constexpr int H = N / 2;
+  constexpr bool ODD = N & 1;
+  T e[H], o[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    e[i] = u[i] + u[N - 1 - i];
+    o[i] = u[i] - u[N - 1 - i];
+  }
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    T ev = ODD ? a.ec[q] * u[H] : T(0), od = 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      ev += a.ep[q * H + i] * e[i];
+      od += a.op[q * H + i] * o[i];
+    }
+    out[q] = ev + od;
+    out[N - 1 - q] = SG > 0 ? ev - od : od - ev;
+  }
+  if constexpr (ODD) {
+    T m = SG > 0 ? a.mid[H] * u[H] : T(0);   // the middle entry vanishes if antisymmetric
+#pragma unroll
+    for (int i = 0; i < H; ++i) m += a.mid[i] * (SG > 0 ? e[i] : o[i]);
+    out[H] = m;
+  }
+}
+
+// out = A^T u with the same even-odd coefficients.
+template <int N, int SG, typename T>
+__host__ __device__ __forceinline__ void eo_apply_t(const EO<N, T> &a, const T *u, T *out) {
+  constexpr int H = N / 2;
+  constexpr bool ODD = N & 1;
+  T e[H], o[H];
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    e[q] = SG > 0 ? u[q] + u[N - 1 - q] : u[q] - u[N - 1 - q];
+    o[q] = SG > 0 ? u[q] - u[N - 1 - q] : u[q] + u[N - 1 - q];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    T ev = 0, od = 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      ev += a.ep[q * H + i] * e[q];
+      od += a.op[q * H + i] * o[q];
+    }
+    const T mc = ODD ? a.mid[i] * u[H] : T(0);
+    out[i] = ev + od + mc;
+    out[N - 1 - i] = SG > 0 ? ev - od + mc : ev - od - mc;
+  }
+  if constexpr (ODD) {
+    T m = SG > 0 ? a.mid[H] * u[H] : T(0);
+#pragma unroll
+    for (int q = 0; q < H; ++q) m += a.ec[q] * e[q];
+    out[H] = m;
+  }
 }
 
 // Sum over a block of `nthreads` (<= 1024) threads, deterministic order; result valid in

@@ -1,22 +1,26 @@
-// Continuous Q_k Laplacian on hexahedra: matrix-free cell kernels (Sec. 3, eq. mf_eval).
+// Continuous Q_k Laplacian on hexahedra: matrix-free operator kernels (Sec. 3, eq. mf_eval).
 //
-// Thread layout shared by the cell kernels: a work-group of 256 lanes holds
-// CPB = floor(256 / n^2) cells, n^2 lanes per cell (n = k+1).  Each lane owns one line
-// of n points of its cell and keeps it in registers; the 1D contractions along that line
-// run on registers with the 1D matrices as uniform (scalar) operands.  Between
-// contraction directions the cell's n^3 values are transposed through LDS, so every LDS
-// value is written once and read once per direction change.  Lanes are reinterpreted per
-// phase as (x, y) owners of z-lines, (x, z) owners of y-lines or (y, z) owners of
-// x-lines.  LDS index of point (x, y, z) of a cell: z n^2 + y n + x.
+// Cell computation.  n^2 lanes per cell (n = k+1); each lane owns one line of n points
+// of its cell in registers and applies the 1D matrices along that line in even-odd form
+// (Sec. 3: half the products; the coefficients are uniform kernel arguments that fit
+// the scalar registers).  Between contraction directions the cell's n^3 values are
+// transposed through LDS (written once, read once per direction change).  Lanes are
+// reinterpreted per phase as (x, y) owners of z-lines, (x, z) owners of y-lines or (y, z)
+// owners of x-lines.  LDS index of point (x, y, z) of a cell: z n^2 + y n + x.
 //
-// The CG vector is gathered from and scattered to the lexicographic grid directly
-// (indices are computed, no index table); contributions of cells sharing a DoF are
-// combined with hardware FP64/FP32 atomic adds into a destination that the
-// boundary-initialization kernel cleared first.  Dirichlet DoFs are read as zero
-// (eliminated columns) and never written by the cell kernels (identity rows are set by
-// the initialization kernel).
+// Assembly without global atomics.  A work-group owns a brick of SX x BY x BZ cells (a
+// pencil segment along x) and walks it in chunks of CX x BY x BZ cells.  The last
+// contraction of every cell adds its n^3 results straight into the chunk's DoF tile in
+// LDS (LDS atomics; cells of the chunk share faces).  Every grid DoF is owned by exactly
+// one brick (half-open ranges per direction, the last brick also owning the domain's
+// upper plane).  Per chunk the work-group stores the owned DoFs of the tile (Dirichlet
+// DoFs get the identity-row value src), carries the tile's upper x face into the next
+// chunk, and writes the brick's upper y/z (and, at the end of the pencil, x) faces, which
+// belong to neighbouring bricks, to a halo buffer.  A second kernel adds the halo values
+// into the lower faces of each brick.  Deterministic; no clearing pass.
 #include <cmath>
 
+#include "ct_tables.h"
 #include "device_common.h"
 
 namespace mfl {
@@ -25,351 +29,468 @@ namespace {
 
 constexpr int kBlock = 256;
 
+
 template <int K>
 struct Shape {
   static constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, cpb = kBlock / n2;
 };
 
-// ---------------------------------------------------------------------------------------
-// Cartesian cells: constant Jacobian h I, so with exact Gauss quadrature the element
-// operator of eq. (mf_eval) factors into the Kronecker sum
-//   A_e = kappa_e h (K (x) M (x) M + M (x) K (x) M + M (x) M (x) K)
-// of the reference 1D mass M and stiffness K of the GLL basis (the same numbers as the
-// quadrature form, re-associated).  Three contraction directions, 7 n^4 FMA per cell.
-// GRAD: instead of scattering, reduce lambda_c^T A_c^{(kappa=1)} u_c per cell.
-template <int K, typename T, bool GRAD>
-__global__ void __launch_bounds__(kBlock)
-cart_kernel(const T *__restrict__ src, T *__restrict__ dst, const T *__restrict__ kappa,
-            const T *__restrict__ lam, T *__restrict__ grad, int Nc, int N1, T h, int dirichlet,
-            Tab<K + 1, T> tb) {
-  using S = Shape<K>;
-  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, CPB = S::cpb;
-  __shared__ T sm[4][CPB * n3];
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2, i0 = p % n, i1 = p / n;
-  const int64_t ncell = int64_t(Nc) * Nc * Nc;
-  const int64_t cell = int64_t(blk) * CPB + lc;
-  const bool inblk = lc < CPB;
-  const bool active = inblk && cell < ncell;
-  int cx = 0, cy = 0, cz = 0;
-  if (active) {
-    cx = int(cell % Nc);
-    cy = int((cell / Nc) % Nc);
-    cz = int(cell / (int64_t(Nc) * Nc));
-  }
-  const int gx = cx * K + i0, gy = cy * K + i1;
-  const bool bxy = dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1));
-  const int64_t plane = int64_t(N1) * N1;
-  const int64_t base = gx + int64_t(N1) * gy + plane * (int64_t(cz) * K);
-  T *A = sm[0] + lc * n3, *B = sm[1] + lc * n3, *C = sm[2] + lc * n3, *D = sm[3] + lc * n3;
+// Cells per chunk in x, y, z for degree K (n^2 lanes per cell, at most 256 lanes), and
+// chunks per brick along x.
+template <int K> struct Brick;
+template <> struct Brick<1> { static constexpr int x = 4, y = 4, z = 4, chunks = 1; };
+template <> struct Brick<2> { static constexpr int x = 3, y = 3, z = 3, chunks = 1; };
+template <> struct Brick<3> { static constexpr int x = 4, y = 2, z = 2, chunks = 2; };
+template <> struct Brick<4> { static constexpr int x = 2, y = 2, z = 2, chunks = 2; };
+template <> struct Brick<5> { static constexpr int x = 3, y = 2, z = 1, chunks = 2; };
+template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; };
+template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; };
+template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2; };
 
-  // phase 1: z-lines (x = i0, y = i1): gather, then M and K along z
-  if (inblk) {
-    T u[n];
+struct CellCtx {
+  int i0, i1;        // lane coordinates within the cell
+  int cz;            // cell coordinate in z (x, y enter through gx, gy)
+  bool inblk;        // lane belongs to a cell slot of the work-group
+  bool active;       // ... and that cell exists
+  bool bxy;          // lane's z-line lies on a Dirichlet x- or y-face
+  int64_t base;      // grid index of the lane's z-line start
+  int64_t plane;     // N1^2
+  int N1, K, dirichlet;
+};
+
+__device__ __forceinline__ CellCtx make_ctx(int K, int n, int p, bool inblk, bool active, int cx, int cy,
+                                            int cz, int N1, int dirichlet) {
+  CellCtx c;
+  c.i0 = p % n;
+  c.i1 = p / n;
+  c.cz = cz;
+  c.inblk = inblk;
+  c.active = active;
+  const int gx = cx * K + c.i0, gy = cy * K + c.i1;
+  c.bxy = dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1));
+  c.plane = int64_t(N1) * N1;
+  c.base = gx + int64_t(N1) * gy + c.plane * (int64_t(cz) * K);
+  c.N1 = N1;
+  c.K = K;
+  c.dirichlet = dirichlet;
+  return c;
+}
+
+__device__ __forceinline__ bool z_bnd(const CellCtx &c, int l) {
+  return c.bxy || (c.dirichlet && on_boundary(c.cz * c.K + l, c.N1));
+}
+
+// ---------------------------------------------------------------------------------------
+// Cartesian cell: constant Jacobian h I, so with exact Gauss quadrature the element
+// operator of eq. (mf_eval) factors into the Kronecker sum
+//   A_e = scale (K (x) M (x) M + M (x) K (x) M + M (x) M (x) K),  scale = kappa_e h,
+// of the reference 1D mass M and stiffness K of the GLL basis (the same numbers as the
+// quadrature form, re-associated).  Seven 1D applications per line set.
+// Buffers A..D: n^3 each.  TXS == 0: y_e ends in A; TXS > 0: y_e is added (LDS atomics)
+// into `tile` (row stride TXS, plane stride TXS * TYS, this cell's origin at `tile`).
+// Contains 3 work-group barriers.
+template <int K, typename T, int TXS = 0, int TYS = 0>
+__device__ __forceinline__ void cart_cell(const CellCtx &cc, const T *__restrict__ src, T scale, T *A, T *B,
+                                          T *C, T *D, const EOTab<K + 1, T> &eo, T *tile = nullptr) {
+  constexpr int n = K + 1, n2 = n * n;
+  const int i0 = cc.i0, i1 = cc.i1, p = i0 + n * i1;
+  // z-lines (x = i0, y = i1): gather, then M and K along z
+  if (cc.inblk) {
+    T u[n], a[n], b[n];
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const bool bnd = bxy || (dirichlet && on_boundary(cz * K + l, N1));
-      u[l] = (active && !bnd) ? src[base + plane * l] : T(0);
-    }
+    for (int l = 0; l < n; ++l) u[l] = (cc.active && !z_bnd(cc, l)) ? src[cc.base + cc.plane * l] : T(0);
+    eo_apply<n, 1>(eo.M, u, a);
+    eo_apply<n, 1>(eo.K, u, b);
 #pragma unroll
     for (int q = 0; q < n; ++q) {
-      T a = 0, b = 0;
-#pragma unroll
-      for (int l = 0; l < n; ++l) {
-        a += tb.M[q * n + l] * u[l];
-        b += tb.K[q * n + l] * u[l];
-      }
-      A[q * n2 + p] = a;
-      B[q * n2 + p] = b;
+      A[q * n2 + p] = a[q];
+      B[q * n2 + p] = b[q];
     }
   }
   __syncthreads();
-  // phase 2: y-lines (x = i0, z = i1): P = M_y (M_z u), S = K_y (M_z u) + M_y (K_z u)
-  if (inblk) {
-    T a1[n], a2[n];
+  // y-lines (x = i0, z = i1): P = M_y (M_z u), S = K_y (M_z u) + M_y (K_z u)
+  if (cc.inblk) {
+    T a1[n], a2[n], pp[n], s1[n], s2[n];
 #pragma unroll
     for (int b = 0; b < n; ++b) {
       a1[b] = A[i1 * n2 + b * n + i0];
       a2[b] = B[i1 * n2 + b * n + i0];
     }
+    eo_apply<n, 1>(eo.M, a1, pp);
+    eo_apply<n, 1>(eo.K, a1, s1);
+    eo_apply<n, 1>(eo.M, a2, s2);
 #pragma unroll
     for (int q = 0; q < n; ++q) {
-      T pp = 0, ss = 0;
-#pragma unroll
-      for (int b = 0; b < n; ++b) {
-        pp += tb.M[q * n + b] * a1[b];
-        ss += tb.K[q * n + b] * a1[b] + tb.M[q * n + b] * a2[b];
-      }
-      C[i1 * n2 + q * n + i0] = pp;
-      D[i1 * n2 + q * n + i0] = ss;
+      C[i1 * n2 + q * n + i0] = pp[q];
+      D[i1 * n2 + q * n + i0] = s1[q] + s2[q];
     }
   }
   __syncthreads();
-  // phase 3: x-lines (y = i0, z = i1): y = K_x P + M_x S, scaled by kappa h
-  if (inblk) {
-    T pa[n], sa[n];
+  // x-lines (y = i0, z = i1): y = scale (K_x P + M_x S)
+  if (cc.inblk) {
+    T pa[n], sa[n], y1[n], y2[n];
 #pragma unroll
     for (int a = 0; a < n; ++a) {
       pa[a] = C[i1 * n2 + i0 * n + a];
       sa[a] = D[i1 * n2 + i0 * n + a];
     }
-    const T scale = GRAD ? h : (active ? kappa[cell] * h : T(0));
+    eo_apply<n, 1>(eo.K, pa, y1);
+    eo_apply<n, 1>(eo.M, sa, y2);
 #pragma unroll
     for (int q = 0; q < n; ++q) {
-      T y = 0;
-#pragma unroll
-      for (int a = 0; a < n; ++a) y += tb.K[q * n + a] * pa[a] + tb.M[q * n + a] * sa[a];
-      A[i1 * n2 + i0 * n + q] = y * scale;
+      const T y = (y1[q] + y2[q]) * scale;
+      if constexpr (TXS > 0)
+        lds_add(tile + i1 * (TXS * TYS) + i0 * TXS + q, y);
+      else
+        A[i1 * n2 + i0 * n + q] = y;
     }
   }
   __syncthreads();
-  // phase 4: z-lines again: scatter-add (or the per-cell gradient reduction)
-  T partial = 0;
-  if (active) {
-#pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const bool bnd = bxy || (dirichlet && on_boundary(cz * K + l, N1));
-      const T v = A[l * n2 + p];
-      if (!bnd) {
-        if constexpr (GRAD)
-          partial += v * lam[base + plane * l];
-        else
-          atomic_add(dst + base + plane * l, v);
-      }
-    }
-  }
-  if constexpr (GRAD) {
-    if (inblk) B[p] = partial;
-    __syncthreads();
-    if (active && p == 0) {
-      T s = 0;
-      for (int j = 0; j < n2; ++j) s += B[j];
-      grad[cell] = -s;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------------------
-// Curved cells (general isoparametric geometry): the per-quadrature-point tensor
+// Curved cell (general isoparametric geometry): the per-quadrature-point tensor
 // G_q = w_q det J_q J_q^{-1} J_q^{-T} (6 unique entries, computed at setup and streamed
-// from HBM; kappa_c applied on the fly).  Sum factorization in the collocation form:
-// values at the Gauss points v = (S (x) S (x) S) u, reference gradient by the Gauss-point
-// collocation derivative D in each direction, q = kappa G grad v, then the transposed
-// sequence.  12 n^4 + 9 n^3 FMA per cell, 8 LDS transposes, 3 LDS buffers per cell.
-template <int K, typename T, bool GRAD>
-__global__ void __launch_bounds__(kBlock)
-curved_kernel(const T *__restrict__ src, T *__restrict__ dst, const T *__restrict__ kappa,
-              const T *__restrict__ metric, const T *__restrict__ lam, T *__restrict__ grad,
-              int Nc, int N1, int dirichlet, Tab<K + 1, T> tb) {
-  using S = Shape<K>;
-  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, CPB = S::cpb;
-  __shared__ T sm[3][CPB * n3];
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2, i0 = p % n, i1 = p / n;
-  const int64_t ncell = int64_t(Nc) * Nc * Nc;
-  const int64_t cell = int64_t(blk) * CPB + lc;
-  const bool inblk = lc < CPB;
-  const bool active = inblk && cell < ncell;
-  int cx = 0, cy = 0, cz = 0;
-  if (active) {
-    cx = int(cell % Nc);
-    cy = int((cell / Nc) % Nc);
-    cz = int(cell / (int64_t(Nc) * Nc));
-  }
-  const int gx = cx * K + i0, gy = cy * K + i1;
-  const bool bxy = dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1));
-  const int64_t plane = int64_t(N1) * N1;
-  const int64_t base = gx + int64_t(N1) * gy + plane * (int64_t(cz) * K);
-  T *A = sm[0] + lc * n3, *B = sm[1] + lc * n3, *C = sm[2] + lc * n3;
-
+// from HBM, layout [cell][6][q]; kappa applied on the fly).  Collocation form of sum
+// factorization: values at the Gauss points v = (S (x) S (x) S) u, reference gradient by
+// the Gauss-point collocation derivative D per direction, q = kappa G grad v, then the
+// transposed sequence.  Buffers A..C; y_e ends in A (TXS == 0) or is added into `tile` as
+// for cart_cell.  Contains 9 work-group barriers.
+template <int K, typename T, int TXS = 0, int TYS = 0>
+__device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restrict__ src, const T *gm, T kap,
+                                            T *A, T *B, T *C, const EOTab<K + 1, T> &eo,
+                                            T *tile = nullptr) {
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n;
+  const int i0 = cc.i0, i1 = cc.i1, p = i0 + n * i1;
   T g[6][n];
-  T kap = 0;
-  // F1: z-lines (x = i0, y = i1): gather, S along z; issue the metric loads early
-  if (inblk) {
-    T u[n];
+  // F1: z-lines (x = i0, y = i1): gather, S along z; the metric loads are issued here so
+  // that they are in flight during the next phases (gm is a valid cell for every lane)
+  if (cc.inblk) {
+    T u[n], t[n];
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const bool bnd = bxy || (dirichlet && on_boundary(cz * K + l, N1));
-      u[l] = (active && !bnd) ? src[base + plane * l] : T(0);
-    }
-    const T *gm = metric + (active ? cell : 0) * (6 * n3) + p;
+    for (int l = 0; l < n; ++l) u[l] = (cc.active && !z_bnd(cc, l)) ? src[cc.base + cc.plane * l] : T(0);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
 #pragma unroll
-      for (int l = 0; l < n; ++l) g[c][l] = active ? gm[c * n3 + l * n2] : T(0);
-    kap = GRAD ? T(1) : (active ? kappa[cell] : T(0));
+      for (int l = 0; l < n; ++l) g[c][l] = gm[c * n3 + l * n2 + p];
+    eo_apply<n, 1>(eo.S, u, t);
 #pragma unroll
-    for (int q = 0; q < n; ++q) {
-      T a = 0;
-#pragma unroll
-      for (int l = 0; l < n; ++l) a += tb.S[q * n + l] * u[l];
-      A[q * n2 + p] = a;
-    }
+    for (int q = 0; q < n; ++q) A[q * n2 + p] = t[q];
   }
   __syncthreads();
   // F2: y-lines (x = i0, z = i1): S along y
-  if (inblk) {
-    T r[n];
+  if (cc.inblk) {
+    T r[n], t[n];
 #pragma unroll
     for (int b = 0; b < n; ++b) r[b] = A[i1 * n2 + b * n + i0];
+    eo_apply<n, 1>(eo.S, r, t);
 #pragma unroll
-    for (int q = 0; q < n; ++q) {
-      T a = 0;
-#pragma unroll
-      for (int b = 0; b < n; ++b) a += tb.S[q * n + b] * r[b];
-      B[i1 * n2 + q * n + i0] = a;
-    }
+    for (int q = 0; q < n; ++q) B[i1 * n2 + q * n + i0] = t[q];
   }
   __syncthreads();
-  // F3: x-lines (y = i0, z = i1): S along x -> values v at Gauss points; D along x -> gx
-  if (inblk) {
-    T r[n], v[n];
+  // F3: x-lines (y = i0, z = i1): S along x -> values v at the Gauss points; D -> dv/dx
+  if (cc.inblk) {
+    T r[n], v[n], d[n];
 #pragma unroll
     for (int a = 0; a < n; ++a) r[a] = B[i1 * n2 + i0 * n + a];
+    eo_apply<n, 1>(eo.S, r, v);
+    eo_apply<n, -1>(eo.D, v, d);
 #pragma unroll
     for (int q = 0; q < n; ++q) {
-      T a = 0;
-#pragma unroll
-      for (int j = 0; j < n; ++j) a += tb.S[q * n + j] * r[j];
-      v[q] = a;
-    }
-#pragma unroll
-    for (int q = 0; q < n; ++q) {
-      T a = 0;
-#pragma unroll
-      for (int j = 0; j < n; ++j) a += tb.D[q * n + j] * v[j];
       A[i1 * n2 + i0 * n + q] = v[q];
-      C[i1 * n2 + i0 * n + q] = a;
+      C[i1 * n2 + i0 * n + q] = d[q];
     }
   }
   __syncthreads();
-  // F4: y-lines (x = i0, z = i1): D along y -> gy
-  if (inblk) {
-    T r[n];
+  // F4: y-lines (x = i0, z = i1): D along y -> dv/dy
+  if (cc.inblk) {
+    T r[n], d[n];
 #pragma unroll
     for (int b = 0; b < n; ++b) r[b] = A[i1 * n2 + b * n + i0];
+    eo_apply<n, -1>(eo.D, r, d);
 #pragma unroll
-    for (int q = 0; q < n; ++q) {
-      T a = 0;
-#pragma unroll
-      for (int b = 0; b < n; ++b) a += tb.D[q * n + b] * r[b];
-      B[i1 * n2 + q * n + i0] = a;
-    }
+    for (int q = 0; q < n; ++q) B[i1 * n2 + q * n + i0] = d[q];
   }
   __syncthreads();
-  // F5 + B1: z-lines (x = i0, y = i1): D along z -> gz; quadrature-point operation;
-  // first transposed derivative (along z).  Each lane rewrites only its own z-line.
-  if (inblk) {
-    T r[n], gz[n], fx[n], fy[n], fz[n];
+  // F5 + B1: z-lines (x = i0, y = i1): D along z -> dv/dz; quadrature-point operation;
+  // transposed derivative along z.  Each lane rewrites only its own z-line.
+  if (cc.inblk) {
+    T r[n], gz[n], fx[n], fy[n], fz[n], acc[n];
 #pragma unroll
     for (int l = 0; l < n; ++l) r[l] = A[l * n2 + p];
-#pragma unroll
-    for (int q = 0; q < n; ++q) {
-      T a = 0;
-#pragma unroll
-      for (int l = 0; l < n; ++l) a += tb.D[q * n + l] * r[l];
-      gz[q] = a;
-    }
+    eo_apply<n, -1>(eo.D, r, gz);
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       const T ux = C[l * n2 + p], uy = B[l * n2 + p], uz = gz[l];
-      // metric components: 00, 11, 22, 01, 02, 12
+      // metric components 00, 11, 22, 01, 02, 12
       fx[l] = kap * (g[0][l] * ux + g[3][l] * uy + g[4][l] * uz);
       fy[l] = kap * (g[3][l] * ux + g[1][l] * uy + g[5][l] * uz);
       fz[l] = kap * (g[4][l] * ux + g[5][l] * uy + g[2][l] * uz);
     }
+    eo_apply_t<n, -1>(eo.D, fz, acc);
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-      T a = 0;
-#pragma unroll
-      for (int q = 0; q < n; ++q) a += tb.D[q * n + l] * fz[q];
-      A[l * n2 + p] = a;
+      A[l * n2 + p] = acc[l];
       C[l * n2 + p] = fx[l];
       B[l * n2 + p] = fy[l];
     }
   }
   __syncthreads();
   // B2: y-lines (x = i0, z = i1): acc += D^T along y of fy
-  if (inblk) {
-    T f[n];
+  if (cc.inblk) {
+    T f[n], d[n];
 #pragma unroll
     for (int b = 0; b < n; ++b) f[b] = B[i1 * n2 + b * n + i0];
+    eo_apply_t<n, -1>(eo.D, f, d);
 #pragma unroll
-    for (int b = 0; b < n; ++b) {
-      T a = A[i1 * n2 + b * n + i0];
-#pragma unroll
-      for (int q = 0; q < n; ++q) a += tb.D[q * n + b] * f[q];
-      A[i1 * n2 + b * n + i0] = a;
-    }
+    for (int b = 0; b < n; ++b) A[i1 * n2 + b * n + i0] += d[b];
   }
   __syncthreads();
   // B3: x-lines (y = i0, z = i1): acc += D^T along x of fx; S^T along x
-  if (inblk) {
-    T f[n], acc[n];
+  if (cc.inblk) {
+    T f[n], d[n], acc[n], w[n];
 #pragma unroll
     for (int a = 0; a < n; ++a) f[a] = C[i1 * n2 + i0 * n + a];
+    eo_apply_t<n, -1>(eo.D, f, d);
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      T s = A[i1 * n2 + i0 * n + a];
+    for (int a = 0; a < n; ++a) acc[a] = A[i1 * n2 + i0 * n + a] + d[a];
+    eo_apply_t<n, 1>(eo.S, acc, w);
 #pragma unroll
-      for (int q = 0; q < n; ++q) s += tb.D[q * n + a] * f[q];
-      acc[a] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < n; ++q) s += tb.S[q * n + i] * acc[q];
-      B[i1 * n2 + i0 * n + i] = s;
-    }
+    for (int i = 0; i < n; ++i) B[i1 * n2 + i0 * n + i] = w[i];
   }
   __syncthreads();
   // B4: y-lines (x = i0, z = i1): S^T along y
-  if (inblk) {
-    T r[n];
+  if (cc.inblk) {
+    T r[n], w[n];
 #pragma unroll
     for (int b = 0; b < n; ++b) r[b] = B[i1 * n2 + b * n + i0];
+    eo_apply_t<n, 1>(eo.S, r, w);
+#pragma unroll
+    for (int i = 0; i < n; ++i) A[i1 * n2 + i * n + i0] = w[i];
+  }
+  __syncthreads();
+  // B5: z-lines (x = i0, y = i1): S^T along z; y_e back into A (own z-line only) or into
+  // the tile
+  if (cc.inblk) {
+    T r[n], w[n];
+#pragma unroll
+    for (int l = 0; l < n; ++l) r[l] = A[l * n2 + p];
+    eo_apply_t<n, 1>(eo.S, r, w);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < n; ++q) s += tb.S[q * n + i] * r[q];
-      A[i1 * n2 + i * n + i0] = s;
+      if constexpr (TXS > 0)
+        lds_add(tile + i * (TXS * TYS) + i1 * TXS + i0, w[i]);
+      else
+        A[i * n2 + p] = w[i];
     }
   }
   __syncthreads();
-  // B5: z-lines (x = i0, y = i1): S^T along z, then scatter-add (or gradient reduction)
-  T partial = 0;
-  if (active) {
-    T r[n];
+}
+
+// ---------------------------------------------------------------------------------------
+// Brick apply kernel.
+struct BrickGrid {
+  int Nc, N1;
+  int sx;              // cells per brick in x (multiple of the chunk width)
+  int nbx, nby, nbz;   // bricks per direction
+  int dirichlet;
+};
+
+// Halo record of a brick (upper faces owned by neighbouring bricks), M = brick extent in
+// DoF intervals: the x face (MY+1)(MZ+1) [Z][Y], then the y face without x = MX,
+// MX (MZ+1) [Z][X], then the z face without x = MX and y = MY, MX MY [Y][X].  x is the
+// fastest index of the y and z faces, so their reads and writes are coalesced.
+__host__ __device__ __forceinline__ int halo_size(int MX, int MY, int MZ) {
+  return (MY + 1) * (MZ + 1) + MX * (MZ + 1) + MX * MY;
+}
+
+__device__ __forceinline__ int halo_index(int X, int Y, int Z, int MX, int MY, int MZ) {
+  const int fx = Z * (MY + 1) + Y;
+  const int fy = (MY + 1) * (MZ + 1) + Z * MX + X;
+  const int fz = (MY + 1) * (MZ + 1) + MX * (MZ + 1) + Y * MX + X;
+  return X == MX ? fx : (Y == MY ? fy : fz);
+}
+
+template <int K, typename T, bool CURVED>
+__global__ void __launch_bounds__(kBlock)
+apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ halo,
+                   const T *__restrict__ kappa, const T *__restrict__ metric, BrickGrid bg, T h) {
+  constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
+  using S = Shape<K>;
+  using Bk = Brick<K>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
+  constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ, NCH = Bk::chunks;
+  static_assert(CPB * n2 <= kBlock, "chunk does not fit the work-group");
+  constexpr int MX = NCH * CX * K, MY = BY * K, MZ = BZ * K;   // brick extent in DoF intervals
+  constexpr int TX = MX + 1, TY = MY + 1, TZ = MZ + 1;
+  constexpr int NBUF = CURVED ? 3 : 4;
+  constexpr int ITEMS = TX * TY * TZ, ITERS = (ITEMS + kBlock - 1) / kBlock;
+  __shared__ T sm[NBUF][CPB * n3];
+  __shared__ T tile[ITEMS];
+
+  const int nb = bg.nbx * bg.nby * bg.nbz;
+  const int brick = xcd_block(blockIdx.x, nb);
+  const int bx = brick % bg.nbx, by = (brick / bg.nbx) % bg.nby, bz = brick / (bg.nbx * bg.nby);
+  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2;
+  const int lx = lc % CX, ly = (lc / CX) % BY, lz = lc / (CX * BY);
+  const bool inblk = lc < CPB;
+  const int Nc = bg.Nc, N1 = bg.N1;
+  const int cx0 = bx * NCH * CX, cy = by * BY + ly, cz = bz * BZ + lz;
+  const int nchunks = min(NCH, (Nc - cx0 + CX - 1) / CX);
+  const int slot = inblk ? lc : 0;
+  T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[2] + slot * n3;
+
 #pragma unroll
-    for (int l = 0; l < n; ++l) r[l] = A[l * n2 + p];
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < n; ++q) s += tb.S[q * n + i] * r[q];
-      const bool bnd = bxy || (dirichlet && on_boundary(cz * K + i, N1));
-      if (!bnd) {
-        if constexpr (GRAD)
-          partial += s * lam[base + plane * i];
-        else
-          atomic_add(dst + base + plane * i, s);
-      }
+  for (int it = 0; it < ITERS; ++it) {
+    const int i = t + it * kBlock;
+    if (ITEMS % kBlock == 0 || i < ITEMS) tile[i] = T(0);
+  }
+  // chunks of CX x BY x BZ cells; each cell adds its local result into the brick tile
+  // (the cell functions contain barriers before their first tile access)
+  for (int j = 0; j < nchunks; ++j) {
+    const int cx = cx0 + j * CX + lx;
+    const bool active = inblk && cx < Nc && cy < Nc && cz < Nc;
+    const int64_t cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
+    const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, bg.dirichlet);
+    T *ctile = tile + (lz * K) * (TX * TY) + (ly * K) * TX + (j * CX + lx) * K;
+    if constexpr (CURVED) {
+      const T kap = active ? kappa[cell] : T(0);
+      curved_cell<K, T, TX, TY>(cc, src, metric + cell * (6 * n3), kap, A, B, C, eo, ctile);
+    } else {
+      T *D = sm[NBUF - 1] + slot * n3;
+      const T scale = active ? kappa[cell] * h : T(0);
+      cart_cell<K, T, TX, TY>(cc, src, scale, A, B, C, D, eo, ctile);
     }
   }
-  if constexpr (GRAD) {
-    if (inblk) C[p] = partial;
-    __syncthreads();
-    if (active && p == 0) {
-      T s = 0;
-      for (int j = 0; j < n2; ++j) s += C[j];
-      grad[cell] = -s;
-    }
+  // owned DoFs -> dst (Dirichlet: identity row), upper faces of inner bricks -> halo record
+  const bool lastx = bx == bg.nbx - 1, lasty = by == bg.nby - 1, lastz = bz == bg.nbz - 1;
+  const int64_t plane = int64_t(N1) * N1;
+  const int gx0 = cx0 * K, gy0 = by * MY, gz0 = bz * MZ;
+  T *hrec = halo + int64_t(brick) * halo_size(MX, MY, MZ);
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int i0 = t + it * kBlock;
+    const bool in_tile = ITEMS % kBlock == 0 || i0 < ITEMS;
+    const int i = in_tile ? i0 : 0;
+    const int X = i % TX, Y = (i / TX) % TY, Z = i / (TX * TY);
+    const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
+    const bool valid = in_tile && gx < N1 && gy < N1 && gz < N1;
+    const bool is_halo = (X == MX && !lastx) || (Y == MY && !lasty) || (Z == MZ && !lastz);
+    const int64_t g = gx + int64_t(N1) * gy + plane * gz;
+    const bool bnd = bg.dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1));
+    T *addr = is_halo ? hrec + halo_index(X, Y, Z, MX, MY, MZ) : dst + g;
+    const T v = tile[i];
+    const T out = (valid && bnd && !is_halo) ? src[g] : v;
+    if (valid) *addr = out;
   }
 }
 
-// dst = src on Dirichlet DoFs, 0 elsewhere (the cell kernels then add into dst).
+// dst += halo contributions on the lower faces of every brick (DoFs whose index is a
+// positive multiple of the brick extent M in some direction).  Each such DoF is visited
+// once (x faces, then y faces off x faces, then z faces off both; x is the fastest index
+// within the y and z faces) and sums, in a fixed order, the upper-face values of the 1, 3
+// or 7 lower bricks sharing it.  32-bit index arithmetic (checked on the host).
+template <int K, typename T>
+__global__ void __launch_bounds__(kBlock)
+halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
+  constexpr int MY = Brick<K>::y * K, MZ = Brick<K>::z * K;
+  const int MX = bg.sx * K;
+  const unsigned N1 = bg.N1, P = N1 * N1;
+  const unsigned fx = unsigned(bg.nbx - 1) * P, fy = unsigned(bg.nby - 1) * P,
+                 fz = unsigned(bg.nbz - 1) * P;
+  const unsigned total = fx + fy + fz;
+  const int hs = halo_size(MX, MY, MZ);
+  for (unsigned id = blockIdx.x * kBlock + threadIdx.x; id < total; id += gridDim.x * kBlock) {
+    int g[3];
+    if (id < fx) {
+      const unsigned f = id / P, r = id - f * P;
+      g[0] = int(f + 1) * MX;
+      g[2] = int(r / N1);
+      g[1] = int(r - unsigned(g[2]) * N1);
+    } else if (id < fx + fy) {
+      const unsigned q = id - fx, f = q / P, r = q - f * P;
+      g[1] = int(f + 1) * MY;
+      g[2] = int(r / N1);
+      g[0] = int(r - unsigned(g[2]) * N1);
+      if (g[0] % MX == 0 && g[0] / MX >= 1 && g[0] / MX < bg.nbx) continue;   // on an x face
+    } else {
+      const unsigned q = id - fx - fy, f = q / P, r = q - f * P;
+      g[2] = int(f + 1) * MZ;
+      g[1] = int(r / N1);
+      g[0] = int(r - unsigned(g[1]) * N1);
+      if (g[0] % MX == 0 && g[0] / MX >= 1 && g[0] / MX < bg.nbx) continue;
+      if (g[1] % MY == 0 && g[1] / MY >= 1 && g[1] / MY < bg.nby) continue;
+    }
+    if (bg.dirichlet && (on_boundary(g[0], N1) || on_boundary(g[1], N1) || on_boundary(g[2], N1)))
+      continue;
+    const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
+    int b[3], X[3];
+    bool sh[3];
+    for (int d = 0; d < 3; ++d) {
+      b[d] = min(g[d] / M[d], NB[d] - 1);
+      X[d] = g[d] - b[d] * M[d];
+      sh[d] = X[d] == 0 && b[d] > 0;
+    }
+    T s = 0;
+    for (int m = 1; m < 8; ++m) {
+      if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
+      const int ob0 = b[0] - (m & 1), ob1 = b[1] - ((m >> 1) & 1), ob2 = b[2] - ((m >> 2) & 1);
+      const int tx = (m & 1) ? MX : X[0], ty = (m & 2) ? MY : X[1], tz = (m & 4) ? MZ : X[2];
+      const int64_t ob = ob0 + int64_t(bg.nbx) * (ob1 + int64_t(bg.nby) * ob2);
+      s += halo[ob * hs + halo_index(tx, ty, tz, MX, MY, MZ)];
+    }
+    dst[g[0] + int64_t(N1) * (g[1] + int64_t(N1) * g[2])] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-cell gradient kernel: g_c = -lambda_c^T A_c^{(kappa=1)} u_c (CPB cells per group).
+template <int K, typename T, bool CURVED>
+__global__ void __launch_bounds__(kBlock)
+kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restrict__ grad,
+                  const T *__restrict__ metric, int Nc, int N1, T h, int dirichlet) {
+  constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
+  using S = Shape<K>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, CPB = S::cpb;
+  constexpr int NBUF = CURVED ? 3 : 4;
+  __shared__ T sm[NBUF][CPB * n3];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2;
+  const int64_t ncell = int64_t(Nc) * Nc * Nc;
+  const int64_t cell = int64_t(blk) * CPB + lc;
+  const bool inblk = lc < CPB;
+  const bool active = inblk && cell < ncell;
+  int cx = 0, cy = 0, cz = 0;
+  if (active) {
+    cx = int(cell % Nc);
+    cy = int((cell / Nc) % Nc);
+    cz = int(cell / (int64_t(Nc) * Nc));
+  }
+  const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, dirichlet);
+  const int slot = inblk ? lc : 0;
+  T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[2] + slot * n3;
+  if constexpr (CURVED) {
+    curved_cell<K, T>(cc, u, metric + (active ? cell : 0) * (6 * n3), T(1), A, B, C, eo);
+  } else {
+    T *D = sm[NBUF - 1] + slot * n3;
+    cart_cell<K, T>(cc, u, active ? h : T(0), A, B, C, D, eo);
+  }
+  T partial = 0;
+  if (active) {
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+      if (!z_bnd(cc, l)) partial += A[l * n2 + p] * lam[cc.base + cc.plane * l];
+  }
+  if (inblk) B[p] = partial;   // B is not used after the cell computation
+  __syncthreads();
+  if (active && p == 0) {
+    T s = 0;
+    for (int j = 0; j < n2; ++j) s += B[j];
+    grad[cell] = -s;
+  }
+}
+
+// dst = src on Dirichlet DoFs, 0 elsewhere.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 boundary_init_kernel(const T *__restrict__ src, T *__restrict__ dst, int N1, int dirichlet) {
@@ -382,208 +503,51 @@ boundary_init_kernel(const T *__restrict__ src, T *__restrict__ dst, int N1, int
   }
 }
 
-// ---------------------------------------------------------------------------------------
-// Setup kernels (FP64).
-
-// Per cell and Gauss point: node positions of the isoparametric map (Gauss-Lobatto
-// support points of x + a sin(pi x) sin(pi y) sin(pi z) (1,1,1)), J_q = sum_i x_i (x)
-// grad phi_i(xi_q), and G_q = w_q det J_q J_q^{-1} J_q^{-T}, stored [cell][6][q] in FP64
-// and FP32 (components 00, 11, 22, 01, 02, 12).
-template <int K>
-__global__ void __launch_bounds__(kBlock)
-metric_kernel(double *__restrict__ m64, float *__restrict__ m32, int Nc, double h, double amp,
-              Tab<K + 1, double> tb) {
-  constexpr int n = K + 1, n3 = n * n * n;
-  __shared__ double S[n * n], Sd[n * n], gll[n], w[n];
-  for (int i = threadIdx.x; i < n * n; i += kBlock) {
-    S[i] = tb.S[i];
-    Sd[i] = tb.Sd[i];
-  }
-  if (threadIdx.x < n) {
-    gll[threadIdx.x] = tb.gll[threadIdx.x];
-    w[threadIdx.x] = tb.w[threadIdx.x];
-  }
-  __syncthreads();
-  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
-  for (int64_t id = blockIdx.x * int64_t(kBlock) + threadIdx.x; id < total;
-       id += int64_t(gridDim.x) * kBlock) {
-    const int64_t cell = id / n3;
-    const int q = int(id - cell * n3), q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
-    const int c[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
-    double X[3][n], s1[3][n];
-    for (int d = 0; d < 3; ++d)
-      for (int i = 0; i < n; ++i) {
-        X[d][i] = (c[d] + gll[i]) * h;
-        s1[d][i] = sin(M_PI * X[d][i]);
-      }
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int i2 = 0; i2 < n; ++i2)
-      for (int i1 = 0; i1 < n; ++i1)
-        for (int i0 = 0; i0 < n; ++i0) {
-          const double disp = amp * s1[0][i0] * s1[1][i1] * s1[2][i2];
-          const double xn[3] = {X[0][i0] + disp, X[1][i1] + disp, X[2][i2] + disp};
-          const double dphi[3] = {Sd[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2],
-                                  S[q0 * n + i0] * Sd[q1 * n + i1] * S[q2 * n + i2],
-                                  S[q0 * n + i0] * S[q1 * n + i1] * Sd[q2 * n + i2]};
-          for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) J[a][b] += xn[a] * dphi[b];
-        }
-    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    double Ji[3][3];
-    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
-    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
-    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
-    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-    const double wd = w[q0] * w[q1] * w[q2] * det;
-    const int cc[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-    for (int e = 0; e < 6; ++e) {
-      const int a = cc[e][0], b = cc[e][1];
-      const double v = wd * (Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2]);
-      m64[cell * (6 * n3) + e * n3 + q] = v;
-      m32[cell * (6 * n3) + e * n3 + q] = float(v);
-    }
-  }
-}
-
-// diag(A) contributions of Cartesian cells: kappa h (K_aa M_bb M_ll + M_aa K_bb M_ll +
-// M_aa M_bb K_ll); assembled with atomics (Dirichlet DoFs skipped, set by the finalize).
-template <int K>
-__global__ void __launch_bounds__(kBlock)
-diag_cart_kernel(double *__restrict__ diag, const double *__restrict__ kappa, int Nc, int N1,
-                 double h, int dirichlet, Tab<K + 1, double> tb) {
-  constexpr int n = K + 1, n3 = n * n * n;
-  __shared__ double Md[n], Kd[n];
-  if (threadIdx.x < n) {
-    Md[threadIdx.x] = tb.M[threadIdx.x * n + threadIdx.x];
-    Kd[threadIdx.x] = tb.K[threadIdx.x * n + threadIdx.x];
-  }
-  __syncthreads();
-  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
-  const int64_t plane = int64_t(N1) * N1;
-  for (int64_t id = blockIdx.x * int64_t(kBlock) + threadIdx.x; id < total;
-       id += int64_t(gridDim.x) * kBlock) {
-    const int64_t cell = id / n3;
-    const int i = int(id - cell * n3), a = i % n, b = (i / n) % n, l = i / (n * n);
-    const int gx = int(cell % Nc) * K + a, gy = int((cell / Nc) % Nc) * K + b,
-              gz = int(cell / (int64_t(Nc) * Nc)) * K + l;
-    if (dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1))) continue;
-    const double v = kappa[cell] * h *
-                     (Kd[a] * Md[b] * Md[l] + Md[a] * Kd[b] * Md[l] + Md[a] * Md[b] * Kd[l]);
-    atomic_add(diag + gx + N1 * int64_t(gy) + plane * gz, v);
-  }
-}
-
-// diag(A) contributions of curved cells: sum_q kappa grad phi_i(q) . G_q grad phi_i(q).
-template <int K>
-__global__ void __launch_bounds__(kBlock)
-diag_curved_kernel(double *__restrict__ diag, const double *__restrict__ kappa,
-                   const double *__restrict__ metric, int Nc, int N1, int dirichlet,
-                   Tab<K + 1, double> tb) {
-  constexpr int n = K + 1, n3 = n * n * n;
-  __shared__ double S[n * n], Sd[n * n];
-  for (int i = threadIdx.x; i < n * n; i += kBlock) {
-    S[i] = tb.S[i];
-    Sd[i] = tb.Sd[i];
-  }
-  __syncthreads();
-  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
-  const int64_t plane = int64_t(N1) * N1;
-  for (int64_t id = blockIdx.x * int64_t(kBlock) + threadIdx.x; id < total;
-       id += int64_t(gridDim.x) * kBlock) {
-    const int64_t cell = id / n3;
-    const int i = int(id - cell * n3), a = i % n, b = (i / n) % n, l = i / (n * n);
-    const int gx = int(cell % Nc) * K + a, gy = int((cell / Nc) % Nc) * K + b,
-              gz = int(cell / (int64_t(Nc) * Nc)) * K + l;
-    if (dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1))) continue;
-    const double *G = metric + cell * (6 * n3);
-    double acc = 0;
-    for (int q = 0; q < n3; ++q) {
-      const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
-      const double d0 = Sd[q0 * n + a] * S[q1 * n + b] * S[q2 * n + l];
-      const double d1 = S[q0 * n + a] * Sd[q1 * n + b] * S[q2 * n + l];
-      const double d2 = S[q0 * n + a] * S[q1 * n + b] * Sd[q2 * n + l];
-      acc += G[q] * d0 * d0 + G[n3 + q] * d1 * d1 + G[2 * n3 + q] * d2 * d2 +
-             2.0 * (G[3 * n3 + q] * d0 * d1 + G[4 * n3 + q] * d0 * d2 + G[5 * n3 + q] * d1 * d2);
-    }
-    atomic_add(diag + gx + N1 * int64_t(gy) + plane * gz, kappa[cell] * acc);
-  }
-}
-
-// Right-hand side b_i = sum_q w_q det J_q f(x_q) phi_i(xi_q), f = 3 pi^2 sin sin sin, with
-// x_q the isoparametric image of the Gauss point.  One work-group per cell.
-template <int K>
-__global__ void __launch_bounds__(kBlock)
-rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double amp, Tab<K + 1, double> tb) {
-  constexpr int n = K + 1, n3 = n * n * n;
-  __shared__ double S[n * n], Sd[n * n], gll[n], w[n], fw[n3];
-  for (int i = threadIdx.x; i < n * n; i += kBlock) {
-    S[i] = tb.S[i];
-    Sd[i] = tb.Sd[i];
-  }
-  if (threadIdx.x < n) {
-    gll[threadIdx.x] = tb.gll[threadIdx.x];
-    w[threadIdx.x] = tb.w[threadIdx.x];
-  }
-  __syncthreads();
-  const int64_t cell = blockIdx.x;
-  const int c[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
-  for (int q = threadIdx.x; q < n3; q += kBlock) {
-    const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
-    double X[3][n], s1[3][n];
-    for (int d = 0; d < 3; ++d)
-      for (int i = 0; i < n; ++i) {
-        X[d][i] = (c[d] + gll[i]) * h;
-        s1[d][i] = sin(M_PI * X[d][i]);
-      }
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, xq[3] = {0, 0, 0};
-    for (int i2 = 0; i2 < n; ++i2)
-      for (int i1 = 0; i1 < n; ++i1)
-        for (int i0 = 0; i0 < n; ++i0) {
-          const double disp = amp * s1[0][i0] * s1[1][i1] * s1[2][i2];
-          const double xn[3] = {X[0][i0] + disp, X[1][i1] + disp, X[2][i2] + disp};
-          const double phi = S[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2];
-          const double dphi[3] = {Sd[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2],
-                                  S[q0 * n + i0] * Sd[q1 * n + i1] * S[q2 * n + i2],
-                                  S[q0 * n + i0] * S[q1 * n + i1] * Sd[q2 * n + i2]};
-          for (int a = 0; a < 3; ++a) {
-            xq[a] += xn[a] * phi;
-            for (int bb = 0; bb < 3; ++bb) J[a][bb] += xn[a] * dphi[bb];
-          }
-        }
-    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    const double f = 3.0 * M_PI * M_PI * sin(M_PI * xq[0]) * sin(M_PI * xq[1]) * sin(M_PI * xq[2]);
-    fw[q] = w[q0] * w[q1] * w[q2] * det * f;
-  }
-  __syncthreads();
-  const int64_t plane = int64_t(N1) * N1;
-  for (int i = threadIdx.x; i < n3; i += kBlock) {
-    const int a = i % n, bb = (i / n) % n, l = i / (n * n);
-    const int gx = c[0] * K + a, gy = c[1] * K + bb, gz = c[2] * K + l;
-    if (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1)) continue;
-    double s = 0;
-    for (int q = 0; q < n3; ++q) {
-      const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
-      s += S[q0 * n + a] * S[q1 * n + bb] * S[q2 * n + l] * fw[q];
-    }
-    atomic_add(b + gx + N1 * int64_t(gy) + plane * gz, s);
-  }
-}
-
 inline int grid_for(int64_t items, int cap = 65536) {
   int64_t g = (items + kBlock - 1) / kBlock;
   return int(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// Bricks: chunk shape from Brick<K>; the x extent is a multiple of the chunk width chosen so
+// that there are about MFL_TARGET_BRICKS bricks (enough work-groups to fill the chip) when
+// the mesh allows, which keeps the strided x-face halos to a few planes.
+template <int K>
+BrickGrid brick_grid(int Nc, int N1, int dirichlet) {
+  BrickGrid bg;
+  bg.Nc = Nc;
+  bg.N1 = N1;
+  bg.sx = Brick<K>::x * Brick<K>::chunks;
+  bg.nbx = (Nc + bg.sx - 1) / bg.sx;
+  bg.nby = (Nc + Brick<K>::y - 1) / Brick<K>::y;
+  bg.nbz = (Nc + Brick<K>::z - 1) / Brick<K>::z;
+  bg.dirichlet = dirichlet;
+  return bg;
+}
+
 }  // namespace
+
+int64_t cg_halo_elements(int k, int Nc) {
+  BrickGrid bg{};
+  int my = 0, mz = 0;
+#define CASE(K)                              \
+  bg = brick_grid<K>(Nc, K * Nc + 1, 1);     \
+  my = Brick<K>::y * K;                      \
+  mz = Brick<K>::z * K;                      \
+  break
+  switch (k) {
+    case 1: CASE(1);
+    case 2: CASE(2);
+    case 3: CASE(3);
+    case 4: CASE(4);
+    case 5: CASE(5);
+    case 6: CASE(6);
+    case 7: CASE(7);
+    case 8: CASE(8);
+    default: return 0;
+  }
+#undef CASE
+  return int64_t(bg.nbx) * bg.nby * bg.nbz * halo_size(bg.sx * k, my, mz);
+}
 
 hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
                                 void *dst, hipStream_t s) {
@@ -597,31 +561,49 @@ hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, con
 }
 
 template <int K, typename T>
-static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, T> &tab,
-                             const T *kappa, const T *metric, const T *src, T *dst, hipStream_t s) {
-  constexpr int CPB = Shape<K>::cpb;
-  const int grid = int((L.ncells + CPB - 1) / CPB);
-  const int dir = c.p.bc == MFL_BC_DIRICHLET;
-  const Tab<K + 1, T> tb = shrink_tab<K + 1, T>(tab);
+static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, T> &tab, const T *kappa,
+                             const T *metric, const T *src, T *dst, T *halo, hipStream_t s) {
+  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, c.p.bc == MFL_BC_DIRICHLET);
+  const int nb = bg.nbx * bg.nby * bg.nbz;
+  (void)tab;
   if (c.p.geometry == MFL_GEOM_CURVED)
-    curved_kernel<K, T, false><<<grid, kBlock, 0, s>>>(src, dst, kappa, metric, nullptr, nullptr,
-                                                      L.Nc, L.N1, dir, tb);
+    apply_brick_kernel<K, T, true><<<nb, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
   else
-    cart_kernel<K, T, false><<<grid, kBlock, 0, s>>>(src, dst, kappa, nullptr, nullptr, L.Nc, L.N1,
-                                                    T(L.h), dir, tb);
+    apply_brick_kernel<K, T, false><<<nb, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+  return hipGetLastError();
+}
+
+template <int K, typename T>
+static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *halo, hipStream_t s) {
+  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, c.p.bc == MFL_BC_DIRICHLET);
+  const int64_t total = int64_t(bg.nbx - 1 + bg.nby - 1 + bg.nbz - 1) * L.N1 * L.N1;
+  if (total == 0) return hipSuccess;
+  if (total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit face index space
+  halo_add_kernel<K, T><<<grid_for(total, 16384), kBlock, 0, s>>>(dst, halo, bg);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
                            hipStream_t s) {
-  hipError_t e = launch_boundary_init(c, L, dtype, src, dst, s);
-  if (e != hipSuccess) return e;
   if (dtype == MFL_F64) {
-#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, s)
+#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   } else {
-#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, s)
+#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s) {
+  if (dtype == MFL_F64) {
+#define CASE(K) return cg_halo_k<K, double>(c, L, (double *)dst, (const double *)L.halo, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else {
+#define CASE(K) return cg_halo_k<K, float>(c, L, (float *)dst, (const float *)L.halo, s)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }
@@ -634,13 +616,10 @@ static hipError_t kappa_grad_k(const Context &c, const Level &L, const double *u
   constexpr int CPB = Shape<K>::cpb;
   const int grid = int((L.ncells + CPB - 1) / CPB);
   const int dir = c.p.bc == MFL_BC_DIRICHLET;
-  const Tab<K + 1, double> tb = shrink_tab<K + 1, double>(c.tab64);
   if (c.p.geometry == MFL_GEOM_CURVED)
-    curved_kernel<K, double, true><<<grid, kBlock, 0, s>>>(u, nullptr, L.kappa64, L.metric64, lam,
-                                                          grad, L.Nc, L.N1, dir, tb);
+    kappa_grad_kernel<K, double, true><<<grid, kBlock, 0, s>>>(u, lam, grad, L.metric64, L.Nc, L.N1, L.h, dir);
   else
-    cart_kernel<K, double, true><<<grid, kBlock, 0, s>>>(u, nullptr, L.kappa64, lam, grad, L.Nc,
-                                                        L.N1, L.h, dir, tb);
+    kappa_grad_kernel<K, double, false><<<grid, kBlock, 0, s>>>(u, lam, grad, nullptr, L.Nc, L.N1, L.h, dir);
   return hipGetLastError();
 }
 
@@ -650,55 +629,6 @@ hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *
   MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s) {
-  const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
-#define CASE(K)                                                                                \
-  metric_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.metric64, L.metric32, L.Nc, L.h,        \
-                                                      c.p.curve_amp, shrink_tab<K + 1, double>(c.tab64)); \
-  break
-  MFL_DISPATCH_K(c.k, CASE)
-#undef CASE
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s) {
-  const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
-  const int dir = c.p.bc == MFL_BC_DIRICHLET;
-  hipError_t e = launch_fill(L.diag64, MFL_F64, L.ndofs, 0.0, s);
-  if (e != hipSuccess) return e;
-  if (c.p.geometry == MFL_GEOM_CURVED) {
-#define CASE(K)                                                                                  \
-  diag_curved_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.diag64, L.kappa64, L.metric64, L.Nc, \
-                                                           L.N1, dir, shrink_tab<K + 1, double>(c.tab64)); \
-  break
-    MFL_DISPATCH_K(c.k, CASE)
-#undef CASE
-  } else {
-#define CASE(K)                                                                               \
-  diag_cart_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.diag64, L.kappa64, L.Nc, L.N1, L.h,  \
-                                                         dir, shrink_tab<K + 1, double>(c.tab64)); \
-  break
-    MFL_DISPATCH_K(c.k, CASE)
-#undef CASE
-  }
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_diag_finalize(c, L, s);
-}
-
-hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStream_t s) {
-  hipError_t e = launch_fill(b, MFL_F64, L.ndofs, 0.0, s);
-  if (e != hipSuccess) return e;
-  const double amp = c.p.geometry == MFL_GEOM_CURVED ? c.p.curve_amp : 0.0;
-#define CASE(K)                                                                              \
-  rhs_kernel<K><<<int(L.ncells), kBlock, 0, s>>>(b, L.Nc, L.N1, L.h, amp,                     \
-                                                  shrink_tab<K + 1, double>(c.tab64));        \
-  break
-  MFL_DISPATCH_K(c.k, CASE)
-#undef CASE
-  return hipGetLastError();
 }
 
 }  // namespace mfl

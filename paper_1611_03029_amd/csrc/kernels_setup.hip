@@ -1,0 +1,263 @@
+// Setup kernels of the continuous Q_k operator (FP64): per-quadrature-point metric of
+// curved cells, the matrix diagonal for the Jacobi smoother, and the sine right-hand side.
+#include <cmath>
+
+#include "device_common.h"
+
+namespace mfl {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+
+// Per cell and Gauss point: node positions of the isoparametric map (Gauss-Lobatto
+// support points of x + a sin(pi x) sin(pi y) sin(pi z) (1,1,1)), J_q = sum_i x_i (x)
+// grad phi_i(xi_q), and G_q = w_q det J_q J_q^{-1} J_q^{-T}, stored [cell][6][q] in FP64
+// and FP32 (components 00, 11, 22, 01, 02, 12).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+metric_kernel(double *__restrict__ m64, float *__restrict__ m32, int Nc, double h, double amp,
+              Tab<K + 1, double> tb) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  __shared__ double S[n * n], Sd[n * n], gll[n], w[n];
+  for (int i = threadIdx.x; i < n * n; i += kBlock) {
+    S[i] = tb.S[i];
+    Sd[i] = tb.Sd[i];
+  }
+  if (threadIdx.x < n) {
+    gll[threadIdx.x] = tb.gll[threadIdx.x];
+    w[threadIdx.x] = tb.w[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
+  for (int64_t id = blockIdx.x * int64_t(kBlock) + threadIdx.x; id < total;
+       id += int64_t(gridDim.x) * kBlock) {
+    const int64_t cell = id / n3;
+    const int q = int(id - cell * n3), q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+    const int c[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
+    double X[3][n], s1[3][n];
+    for (int d = 0; d < 3; ++d)
+      for (int i = 0; i < n; ++i) {
+        X[d][i] = (c[d] + gll[i]) * h;
+        s1[d][i] = sin(M_PI * X[d][i]);
+      }
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int i2 = 0; i2 < n; ++i2)
+      for (int i1 = 0; i1 < n; ++i1)
+        for (int i0 = 0; i0 < n; ++i0) {
+          const double disp = amp * s1[0][i0] * s1[1][i1] * s1[2][i2];
+          const double xn[3] = {X[0][i0] + disp, X[1][i1] + disp, X[2][i2] + disp};
+          const double dphi[3] = {Sd[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2],
+                                  S[q0 * n + i0] * Sd[q1 * n + i1] * S[q2 * n + i2],
+                                  S[q0 * n + i0] * S[q1 * n + i1] * Sd[q2 * n + i2]};
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) J[a][b] += xn[a] * dphi[b];
+        }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double Ji[3][3];
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    const double wd = w[q0] * w[q1] * w[q2] * det;
+    const int cc[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    for (int e = 0; e < 6; ++e) {
+      const int a = cc[e][0], b = cc[e][1];
+      const double v = wd * (Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2]);
+      m64[cell * (6 * n3) + e * n3 + q] = v;
+      m32[cell * (6 * n3) + e * n3 + q] = float(v);
+    }
+  }
+}
+
+// diag(A) contributions of Cartesian cells: kappa h (K_aa M_bb M_ll + M_aa K_bb M_ll +
+// M_aa M_bb K_ll); assembled with atomics (Dirichlet DoFs skipped, set by the finalize).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+diag_cart_kernel(double *__restrict__ diag, const double *__restrict__ kappa, int Nc, int N1,
+                 double h, int dirichlet, Tab<K + 1, double> tb) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  __shared__ double Md[n], Kd[n];
+  if (threadIdx.x < n) {
+    Md[threadIdx.x] = tb.M[threadIdx.x * n + threadIdx.x];
+    Kd[threadIdx.x] = tb.K[threadIdx.x * n + threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
+  const int64_t plane = int64_t(N1) * N1;
+  for (int64_t id = blockIdx.x * int64_t(kBlock) + threadIdx.x; id < total;
+       id += int64_t(gridDim.x) * kBlock) {
+    const int64_t cell = id / n3;
+    const int i = int(id - cell * n3), a = i % n, b = (i / n) % n, l = i / (n * n);
+    const int gx = int(cell % Nc) * K + a, gy = int((cell / Nc) % Nc) * K + b,
+              gz = int(cell / (int64_t(Nc) * Nc)) * K + l;
+    if (dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1))) continue;
+    const double v = kappa[cell] * h *
+                     (Kd[a] * Md[b] * Md[l] + Md[a] * Kd[b] * Md[l] + Md[a] * Md[b] * Kd[l]);
+    atomic_add(diag + gx + N1 * int64_t(gy) + plane * gz, v);
+  }
+}
+
+// diag(A) contributions of curved cells: sum_q kappa grad phi_i(q) . G_q grad phi_i(q).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+diag_curved_kernel(double *__restrict__ diag, const double *__restrict__ kappa,
+                   const double *__restrict__ metric, int Nc, int N1, int dirichlet,
+                   Tab<K + 1, double> tb) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  __shared__ double S[n * n], Sd[n * n];
+  for (int i = threadIdx.x; i < n * n; i += kBlock) {
+    S[i] = tb.S[i];
+    Sd[i] = tb.Sd[i];
+  }
+  __syncthreads();
+  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
+  const int64_t plane = int64_t(N1) * N1;
+  for (int64_t id = blockIdx.x * int64_t(kBlock) + threadIdx.x; id < total;
+       id += int64_t(gridDim.x) * kBlock) {
+    const int64_t cell = id / n3;
+    const int i = int(id - cell * n3), a = i % n, b = (i / n) % n, l = i / (n * n);
+    const int gx = int(cell % Nc) * K + a, gy = int((cell / Nc) % Nc) * K + b,
+              gz = int(cell / (int64_t(Nc) * Nc)) * K + l;
+    if (dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1))) continue;
+    const double *G = metric + cell * (6 * n3);
+    double acc = 0;
+    for (int q = 0; q < n3; ++q) {
+      const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+      const double d0 = Sd[q0 * n + a] * S[q1 * n + b] * S[q2 * n + l];
+      const double d1 = S[q0 * n + a] * Sd[q1 * n + b] * S[q2 * n + l];
+      const double d2 = S[q0 * n + a] * S[q1 * n + b] * Sd[q2 * n + l];
+      acc += G[q] * d0 * d0 + G[n3 + q] * d1 * d1 + G[2 * n3 + q] * d2 * d2 +
+             2.0 * (G[3 * n3 + q] * d0 * d1 + G[4 * n3 + q] * d0 * d2 + G[5 * n3 + q] * d1 * d2);
+    }
+    atomic_add(diag + gx + N1 * int64_t(gy) + plane * gz, kappa[cell] * acc);
+  }
+}
+
+// Right-hand side b_i = sum_q w_q det J_q f(x_q) phi_i(xi_q), f = 3 pi^2 sin sin sin, with
+// x_q the isoparametric image of the Gauss point.  One work-group per cell.
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double amp, Tab<K + 1, double> tb) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  __shared__ double S[n * n], Sd[n * n], gll[n], w[n], fw[n3];
+  for (int i = threadIdx.x; i < n * n; i += kBlock) {
+    S[i] = tb.S[i];
+    Sd[i] = tb.Sd[i];
+  }
+  if (threadIdx.x < n) {
+    gll[threadIdx.x] = tb.gll[threadIdx.x];
+    w[threadIdx.x] = tb.w[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t cell = blockIdx.x;
+  const int c[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
+  for (int q = threadIdx.x; q < n3; q += kBlock) {
+    const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+    double X[3][n], s1[3][n];
+    for (int d = 0; d < 3; ++d)
+      for (int i = 0; i < n; ++i) {
+        X[d][i] = (c[d] + gll[i]) * h;
+        s1[d][i] = sin(M_PI * X[d][i]);
+      }
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, xq[3] = {0, 0, 0};
+    for (int i2 = 0; i2 < n; ++i2)
+      for (int i1 = 0; i1 < n; ++i1)
+        for (int i0 = 0; i0 < n; ++i0) {
+          const double disp = amp * s1[0][i0] * s1[1][i1] * s1[2][i2];
+          const double xn[3] = {X[0][i0] + disp, X[1][i1] + disp, X[2][i2] + disp};
+          const double phi = S[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2];
+          const double dphi[3] = {Sd[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2],
+                                  S[q0 * n + i0] * Sd[q1 * n + i1] * S[q2 * n + i2],
+                                  S[q0 * n + i0] * S[q1 * n + i1] * Sd[q2 * n + i2]};
+          for (int a = 0; a < 3; ++a) {
+            xq[a] += xn[a] * phi;
+            for (int bb = 0; bb < 3; ++bb) J[a][bb] += xn[a] * dphi[bb];
+          }
+        }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const double f = 3.0 * M_PI * M_PI * sin(M_PI * xq[0]) * sin(M_PI * xq[1]) * sin(M_PI * xq[2]);
+    fw[q] = w[q0] * w[q1] * w[q2] * det * f;
+  }
+  __syncthreads();
+  const int64_t plane = int64_t(N1) * N1;
+  for (int i = threadIdx.x; i < n3; i += kBlock) {
+    const int a = i % n, bb = (i / n) % n, l = i / (n * n);
+    const int gx = c[0] * K + a, gy = c[1] * K + bb, gz = c[2] * K + l;
+    if (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1)) continue;
+    double s = 0;
+    for (int q = 0; q < n3; ++q) {
+      const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+      s += S[q0 * n + a] * S[q1 * n + bb] * S[q2 * n + l] * fw[q];
+    }
+    atomic_add(b + gx + N1 * int64_t(gy) + plane * gz, s);
+  }
+}
+
+inline int grid_for(int64_t items, int cap = 65536) {
+  int64_t g = (items + kBlock - 1) / kBlock;
+  return int(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s) {
+  const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
+#define CASE(K)                                                                                \
+  metric_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.metric64, L.metric32, L.Nc, L.h,        \
+                                                      c.p.curve_amp, shrink_tab<K + 1, double>(c.tab64)); \
+  break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s) {
+  const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
+  const int dir = c.p.bc == MFL_BC_DIRICHLET;
+  hipError_t e = launch_fill(L.diag64, MFL_F64, L.ndofs, 0.0, s);
+  if (e != hipSuccess) return e;
+  if (c.p.geometry == MFL_GEOM_CURVED) {
+#define CASE(K)                                                                                  \
+  diag_curved_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.diag64, L.kappa64, L.metric64, L.Nc, \
+                                                           L.N1, dir, shrink_tab<K + 1, double>(c.tab64)); \
+  break
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else {
+#define CASE(K)                                                                               \
+  diag_cart_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.diag64, L.kappa64, L.Nc, L.N1, L.h,  \
+                                                         dir, shrink_tab<K + 1, double>(c.tab64)); \
+  break
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_diag_finalize(c, L, s);
+}
+
+hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStream_t s) {
+  hipError_t e = launch_fill(b, MFL_F64, L.ndofs, 0.0, s);
+  if (e != hipSuccess) return e;
+  const double amp = c.p.geometry == MFL_GEOM_CURVED ? c.p.curve_amp : 0.0;
+#define CASE(K)                                                                              \
+  rhs_kernel<K><<<int(L.ncells), kBlock, 0, s>>>(b, L.Nc, L.N1, L.h, amp,                     \
+                                                  shrink_tab<K + 1, double>(c.tab64));        \
+  break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipGetLastError();
+}
+
+}  // namespace mfl

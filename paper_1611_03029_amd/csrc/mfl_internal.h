@@ -37,6 +37,43 @@ struct Tab {
   T gll[N];
 };
 
+// Even-odd form of an N x N matrix A that is centro-symmetric (A[N-1-q][N-1-i] = A[q][i])
+// or centro-antisymmetric (= -A[q][i]), with H = N/2 and c = H the middle index (odd N):
+//   ep[q][i] = (A[q][i] + A[q][N-1-i]) / 2,  op[q][i] = (A[q][i] - A[q][N-1-i]) / 2  (q, i < H)
+//   ec[q] = A[q][c],  mid[i] = A[c][i] (i < H),  mid[H] = A[c][c].
+// All 1D matrices of the Gauss/Gauss-Lobatto bases have this symmetry (the point sets
+// are symmetric about 1/2), which halves the products of a 1D contraction (Sec. 3).
+template <int N, typename T>
+struct EO {
+  static constexpr int H = N / 2;
+  T ep[H * H];
+  T op[H * H];
+  T ec[H];
+  T mid[H + 1];
+};
+
+template <int N, typename T>
+struct EOTab {
+  EO<N, T> M, K;   // reference mass and stiffness of the GLL basis (centro-symmetric)
+  EO<N, T> S;      // GLL basis at the Gauss points (centro-symmetric)
+  EO<N, T> D;      // Gauss-point collocation derivative (centro-antisymmetric)
+};
+
+template <int N, typename T>
+EO<N, T> make_eo(const double *A) {   // A row-major N x N (row length N)
+  EO<N, T> e{};
+  constexpr int H = N / 2;
+  for (int q = 0; q < H; ++q) {
+    for (int i = 0; i < H; ++i) {
+      e.ep[q * H + i] = T(0.5 * (A[q * N + i] + A[q * N + N - 1 - i]));
+      e.op[q * H + i] = T(0.5 * (A[q * N + i] - A[q * N + N - 1 - i]));
+    }
+    e.ec[q] = (N % 2) ? T(A[q * N + H]) : T(0);
+  }
+  for (int i = 0; i <= H; ++i) e.mid[i] = (N % 2) ? T(A[H * N + i]) : T(0);
+  return e;
+}
+
 // Embedding of the coarse GLL basis in the fine grid lines of one coarse cell:
 // P[f (k+1) + i] = coarse basis i at the f-th of the 2k+1 fine points.
 struct TransferTab {
@@ -57,6 +94,7 @@ struct Level {
   double *dinv64 = nullptr;
   float *diag32 = nullptr;
   float *dinv32 = nullptr;
+  void *halo = nullptr;         // CG apply: upper-face values of every brick (FP64 size)
   // multigrid vectors in the cycle's precision (FP64 on the coarsest level)
   void *b = nullptr, *x = nullptr, *ax = nullptr, *d = nullptr;
   bool mg_f32 = false;          // vectors of this level are float
@@ -77,6 +115,10 @@ struct Context {
   double *partials = nullptr;   // kReduceBlocks doubles
   double *scalars = nullptr;    // device scalars (see enum Scalar)
   double *host_scalars = nullptr;   // pinned host mirror
+  // optional timing of the operator cell kernels of mfl_apply (HIP event pairs)
+  bool profiling = false;
+  int prof_used = 0;
+  std::vector<hipEvent_t> prof_start, prof_stop;
 };
 
 enum Scalar { kRZ = 0, kPQ, kAlpha, kBeta, kRR, kBB, kRZnew, kNumScalars = 16 };
@@ -90,8 +132,11 @@ void build_tables(int k, Tab<kMaxN, double> &t64, Tab<kMaxN, float> &t32, Transf
 // ---- kernel launchers (return hipError_t of the launch) -----------------------
 hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
                                 void *dst, hipStream_t s);
+// CG operator: brick kernel (owned DoFs + halo records), then the halo addition
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
                            hipStream_t s);
+hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s);
+int64_t cg_halo_elements(int k, int Nc);
 hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *u, const double *lam,
                                 double *grad, hipStream_t s);
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s);

@@ -50,6 +50,18 @@ def test_apply_fp64_matches_csr(k, geom):
     assert rel_err(y32.double(), ref) <= 2e-5
 
 
+@pytest.mark.parametrize("k,Nc", [(4, 5), (3, 7), (2, 5), (6, 5), (1, 6)])
+def test_apply_ragged_bricks(k, Nc):
+    """Cell counts that the work-group bricks do not divide (partial bricks at the end)."""
+    box = Box(Nc, k, 0.1)
+    kap = kappa_field(box.n_cells)
+    prob = mfl.Problem(k, Nc, kappa=kap, geometry=mfl.CURVED, curve_amp=0.1)
+    u = uniform_vector(box.n_dofs, 40 + k)
+    assert rel_err(prob.apply(t(u)), o_cg.assemble(box, kap) @ u) <= 1e-12
+    cart = mfl.Problem(k, Nc, kappa=kap)
+    assert rel_err(cart.apply(t(u)), o_cg.assemble(Box(Nc, k), kap) @ u) <= 1e-12
+
+
 @pytest.mark.parametrize("geom", [0.0, 0.1])
 def test_neumann_apply_and_null_space(geom):
     k, Nc = 3, 3
