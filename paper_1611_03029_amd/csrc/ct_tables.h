@@ -162,5 +162,44 @@ struct Tables {
   static constexpr EOTab<N, T> eo = eotab<N, T>();
 };
 
+// DG basis (Lagrange in the N Gauss points of [0,1]): Gauss weights w, reference stiffness
+// Kg[i][j] = sum_q w_q psi_i'(x_q) psi_j'(x_q) in even-odd form, and the basis values and
+// derivatives at the end points: fv0[i] = psi_i(0), fd0[i] = psi_i'(0).  By the symmetry of
+// the points, psi_i(1) = fv0[N-1-i] and psi_i'(1) = -fd0[N-1-i].
+template <int N, typename T>
+struct DGTab {
+  T w[N];
+  T fv0[N], fd0[N];
+  EO<N, T> Kg;
+};
+
+template <int N, typename T>
+constexpr DGTab<N, T> dgtab() {
+  const Rules<N> r = rules<N>();
+  DGTab<N, T> t{};
+  double D[N * N] = {}, Kg[N * N] = {};
+  for (int q = 0; q < N; ++q)
+    for (int i = 0; i < N; ++i) D[q * N + i] = lagrange<N>(r.xg, i, r.xg[q]).dP;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int q = 0; q < N; ++q) s += r.wg[q] * D[q * N + i] * D[q * N + j];
+      Kg[i * N + j] = s;
+    }
+  for (int i = 0; i < N; ++i) {
+    t.w[i] = T(r.wg[i]);
+    const LegVal v = lagrange<N>(r.xg, i, 0.0);
+    t.fv0[i] = T(v.P);
+    t.fd0[i] = T(v.dP);
+  }
+  t.Kg = to_eo<N, T>(Kg);
+  return t;
+}
+
+template <int N, typename T>
+struct DGTables {
+  static constexpr DGTab<N, T> tab = dgtab<N, T>();
+};
+
 }  // namespace ct
 }  // namespace mfl
