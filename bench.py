@@ -1,23 +1,30 @@
 """Benchmark of the matrix-free Laplace hot path on one MI355X.
 
-Timed step: one FP64 operator application dst = A src of the continuous Q4 Laplacian
-on 64^3 curved cells (257^3 = 16,974,593 DoFs; deformation x + 0.1 sin(pi x) sin(pi y)
-sin(pi z) per coordinate; 5 Gauss points per direction; seeded U[-1,1] input already in
-HBM).  value = DoFs / second of that step.
+Timed step (the JSON `value`): one FP64 operator application dst = A src of the
+continuous Q4 Laplacian on 64^3 curved cells (257^3 = 16,974,593 DoFs; deformation
+x + 0.1 sin(pi x) sin(pi y) sin(pi z) per coordinate; 5 Gauss points per direction;
+seeded U[-1,1] input already in HBM).  value = DoFs per second of that step.
 
-Also reported (outside the timed region):
-  * the dominant kernel (the curved-cell operator kernel) timed with HIP events on its
-    stream, against the HBM roofline with the algorithmic bytes of one application;
-  * the FP32 application of the same operator;
-  * GMG-PCG time to solution with the V-cycle in FP32 and in FP64 inside the FP64
-    outer CG (Cartesian 64^3 fine level, levels down to 2^3, Chebyshev(5)-Jacobi,
-    tolerance 1e-10 relative residual, sine right-hand side);
-  * the CPU oracle (element-by-element dense element matrices) timed on the host for a
-    bounded sample of rows of the same workload.
+Also reported, outside the timed region:
+  roofline      the dominant kernel (curved-cell operator kernel) timed with HIP events on
+                its stream, against the HBM roofline with the algorithmic bytes of one
+                application; `traffic` from the committed rocprofv3 counter summary when it
+                was taken on the current kernel source;
+  fp32_apply    the same operator in FP32 (FP32 vectors and geometry factors);
+  small_q2      CG Q2 on 8^3 cells: apply latency and the FP64 GMG-PCG solve;
+  sipg          SIPG Q3 and Q5 on 32^3 cells (FP64 apply);
+  gmg_pcg       GMG-PCG time to solution, V-cycle in FP32 and in FP64 inside the FP64 outer
+                CG, Cartesian 64^3 fine level, levels down to 2^3, Chebyshev(5)-Jacobi,
+                tolerance 1e-10 relative residual, sine right-hand side, degrees 2..6;
+  adjoint       forward solve + adjoint solve + gradient kernel, CG Q3 on 32^3 cells,
+                FP32 V-cycle;
+  cpu_baseline  the CPU oracle (element-by-element dense element matrices) on a bounded
+                sample of rows of the timed workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve-degrees 2,4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve-degrees 2,3,4,5,6]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,11 +36,33 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "matrix-free Laplace apply DoFs/s (FP64) + GMG-PCG time-to-solution FP32-MG vs FP64"
+KERNEL_SOURCES = ["paper_1611_03029_amd/csrc/kernels_cg.hip", "paper_1611_03029_amd/csrc/ct_tables.h",
+                  "paper_1611_03029_amd/csrc/device_common.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_apply_q4_64cubed_curved_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
+    None when the summary is missing or was taken on another version of the kernel."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def apply_bytes(n_dofs, n_cells, q_per_cell, real_bytes, curved=True):
-    """Algorithmic bytes of one application: read src, write dst once, stream the
-    6-entry metric per quadrature point and one kappa per cell."""
+    """Algorithmic bytes of one CG application: read src, write dst once, one kappa per
+    cell, and on curved cells the 6-entry metric per quadrature point."""
     b = 2 * real_bytes * n_dofs + real_bytes * n_cells
     if curved:
         b += 6 * real_bytes * q_per_cell * n_cells
@@ -53,6 +82,56 @@ def time_applies(prob, src, dst, steps, warmup):
     t1 = time.perf_counter()
     launches, kern_ms = prob.profile_stop()
     return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches
+
+
+def calibration_copy(n):
+    """A plain device copy of n doubles (the reference kernel for counter scaling)."""
+    import torch
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": 8 * n, "bytes_written": 8 * n}
+
+
+def small_config(steps):
+    import torch
+    import paper_1611_03029_amd as mfl
+    from seeded_inputs import SEED_CG_Q2_SMALL, uniform_vector
+    prob = mfl.Problem(2, 8, build_mg=True)
+    u = torch.tensor(uniform_vector(prob.n_dofs, SEED_CG_Q2_SMALL), device="cuda")
+    y = torch.empty_like(u)
+    ms, kms, _ = time_applies(prob, u, y, steps, 10)
+    b = prob.rhs_sine()
+    best, its, res = None, 0, 0.0
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, its, res = prob.solve(b, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"n_dofs": prob.n_dofs, "apply_us": ms * 1e3, "kernel_us": kms * 1e3,
+            "pcg_fp64_mg_s": best, "iterations": its, "final_rel_residual": res}
+
+
+def sipg_configs(steps):
+    import torch
+    import paper_1611_03029_amd as mfl
+    from seeded_inputs import SEED_SIPG_Q3, SEED_SIPG_Q5, uniform_vector
+    out = {}
+    for k, seed in ((3, SEED_SIPG_Q3), (5, SEED_SIPG_Q5)):
+        prob = mfl.Problem(k, 32, disc=mfl.SIPG)
+        u = torch.tensor(uniform_vector(prob.n_dofs, seed), device="cuda")
+        y = torch.empty_like(u)
+        ms, kms, _ = time_applies(prob, u, y, steps, 10)
+        byts = 16 * prob.n_dofs
+        out["Q%d_32^3" % k] = {"n_dofs": prob.n_dofs, "ms_per_apply": ms, "kernel_ms": kms,
+                               "dofs_per_s": prob.n_dofs / (ms * 1e-3),
+                               "equiv_dofs_per_s": prob.n_cells * k ** 3 / (ms * 1e-3),
+                               "hbm_frac_16B_per_dof": byts / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del prob
+    return out
 
 
 def solve_comparison(degree, cells, repeats=2):
@@ -83,6 +162,32 @@ def solve_comparison(degree, cells, repeats=2):
     out["speedup_fp32_mg"] = out["fp64_mg"]["time_s"] / out["fp32_mg"]["time_s"]
     out["max_rel_diff_fp32_vs_fp64_solution"] = diff
     return out
+
+
+def adjoint_config():
+    import numpy as np
+    import torch
+    import paper_1611_03029_amd as mfl
+    from seeded_inputs import SEED_KAPPA_FIELD, SEED_KAPPA_PERTURB, gaussian_field
+    Nc, k = 32, 3
+    g = gaussian_field(Nc ** 3, SEED_KAPPA_FIELD, 0.5)
+    prob = mfl.Problem(k, Nc, build_mg=True, mg_precision=mfl.F32, kappa=np.exp(g))
+    b = prob.rhs_sine()
+    prob.set_kappa(np.exp(g + gaussian_field(Nc ** 3, SEED_KAPPA_PERTURB, 0.1)))
+    u_t, _, _ = prob.solve(b, rtol=1e-10)
+    best = None
+    for _ in range(3):
+        kt = torch.tensor(np.exp(g), device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = mfl.PoissonSolve.apply(kt, prob, b, 1e-10, 100)
+        (0.5 * ((u - u_t) ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"n_dofs": prob.n_dofs, "n_cells": prob.n_cells,
+            "forward_adjoint_gradient_s": best,
+            "note": "includes two set_kappa rebuilds (diagonals, eigenvalue estimates)"}
 
 
 def cpu_baseline(budget_s=15.0):
@@ -116,9 +221,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--solve-degrees", default="2,4")
+    ap.add_argument("--solve-degrees", default="2,3,4,5,6")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed step and FP32 apply")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path is single-GPU (multi-GPU sharding is a "
@@ -143,13 +249,10 @@ def main():
     y32 = torch.empty_like(u32)
     ms32, kern32, _ = time_applies(prob, u32, y32, max(args.steps // 2, 10), args.warmup)
     bytes32 = apply_bytes(n, cells, q, 4)
-    del prob, u64, y64, u32, y32
+    del prob, u32, y32, y64
+    calib = calibration_copy(n)
+    del u64
     torch.cuda.empty_cache()
-
-    solves = {}
-    for d in [int(s) for s in args.solve_degrees.split(",") if s.strip()]:
-        solves["Q%d_64^3" % d] = solve_comparison(d, 64)
-        torch.cuda.empty_cache()
 
     result = {
         "metric": METRIC,
@@ -168,16 +271,26 @@ def main():
                    "degree": k, "cells_per_dim": Nc, "n_dofs": n, "geometry": "x+0.1 sin sin sin",
                    "quadrature": "Gauss %d^3" % (k + 1), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "curved_kernel<4,double>", "kernel_ms": kern_ms,
-                     "algorithmic_bytes": bytes64, "timed_launches": launches},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "apply_brick_kernel<4,double,curved>", "kernel_ms": kern_ms,
+                     "algorithmic_bytes": bytes64, "timed_launches": launches,
+                     "kernel_source_hash": kernel_source_hash()},
         "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32,
                        "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
                        "frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "gmg_pcg": solves,
+        "calibration_copy": calib,
         "paper_context": {"cg_curved_q4_dofs_per_s": 4.58e8,
                           "hardware": "2x14-core Xeon E5-2690 v4 (Broadwell), FP64, 393216-cell shell"},
     }
+    if not args.no_extras:
+        result["small_q2"] = small_config(args.steps)
+        result["sipg"] = sipg_configs(args.steps)
+        solves = {}
+        for d in [int(s) for s in args.solve_degrees.split(",") if s.strip()]:
+            solves["Q%d_64^3" % d] = solve_comparison(d, 64)
+            torch.cuda.empty_cache()
+        result["gmg_pcg"] = solves
+        result["adjoint"] = adjoint_config()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(result))
