@@ -28,6 +28,25 @@ __device__ __forceinline__ void lds_add(T *p, T v) {
 
 __device__ __forceinline__ bool on_boundary(int g, int N1) { return g == 0 || g == N1 - 1; }
 
+// Synchronization point among the lanes of one wavefront for data exchanged through LDS.
+// A wavefront's LDS instructions execute in issue order, so only the compiler has to be
+// kept from moving LDS accesses across this point; no instruction is emitted.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Barrier between the phases of a cell computation: a wavefront barrier when every cell
+// lies inside one wavefront (WAVE), a work-group barrier otherwise.
+template <bool WAVE>
+__device__ __forceinline__ void cell_sync() {
+  if constexpr (WAVE)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
 // Copy of the first N*N entries of the kMaxN-sized host tables (rows of length N).
 template <int N, typename T>
 Tab<N, T> shrink_tab(const Tab<kMaxN, T> &t) {

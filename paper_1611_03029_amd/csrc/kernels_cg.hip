@@ -2,22 +2,22 @@
 //
 // Cell computation.  n^2 lanes per cell (n = k+1); each lane owns one line of n points
 // of its cell in registers and applies the 1D matrices along that line in even-odd form
-// (Sec. 3: half the products; the coefficients are uniform kernel arguments that fit
-// the scalar registers).  Between contraction directions the cell's n^3 values are
-// transposed through LDS (written once, read once per direction change).  Lanes are
-// reinterpreted per phase as (x, y) owners of z-lines, (x, z) owners of y-lines or (y, z)
-// owners of x-lines.  LDS index of point (x, y, z) of a cell: z n^2 + y n + x.
+// (Sec. 3: about half the products; the coefficients are compile-time constants, see
+// ct_tables.h).  Between contraction directions the cell's n^3 values are transposed
+// through LDS.  Lanes are reinterpreted per phase as (x, y) owners of z-lines, (x, z)
+// owners of y-lines or (y, z) owners of x-lines.  LDS index of point (x, y, z) of a cell:
+// z n^2 + y n + x.  Where n^2 <= 64 every cell lies inside one wavefront and the phases
+// are separated by wavefront-level synchronization only.
 //
-// Assembly without global atomics.  A work-group owns a brick of SX x BY x BZ cells (a
-// pencil segment along x) and walks it in chunks of CX x BY x BZ cells.  The last
-// contraction of every cell adds its n^3 results straight into the chunk's DoF tile in
-// LDS (LDS atomics; cells of the chunk share faces).  Every grid DoF is owned by exactly
-// one brick (half-open ranges per direction, the last brick also owning the domain's
-// upper plane).  Per chunk the work-group stores the owned DoFs of the tile (Dirichlet
-// DoFs get the identity-row value src), carries the tile's upper x face into the next
-// chunk, and writes the brick's upper y/z (and, at the end of the pencil, x) faces, which
-// belong to neighbouring bricks, to a halo buffer.  A second kernel adds the halo values
-// into the lower faces of each brick.  Deterministic; no clearing pass.
+// Assembly without global atomics.  A work-group owns a brick of cells (a few chunks of
+// CX x BY x BZ cells along x).  The last contraction of every cell adds its n^3 results
+// into the brick's DoF tile in LDS (FP64 LDS atomics; cells share faces).  Every grid DoF
+// is owned by exactly one brick (half-open ranges per direction, the last brick also
+// owning the domain's upper plane).  After its cells the work-group stores the owned DoFs
+// of the tile (Dirichlet DoFs get the identity-row value src) and writes the tile's upper
+// faces, which belong to neighbouring bricks, to the brick's halo record.  A second
+// kernel adds the halo records into the lower faces of each brick.  Deterministic; no
+// clearing pass.
 #include <cmath>
 
 #include "ct_tables.h"
@@ -35,17 +35,40 @@ struct Shape {
   static constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, cpb = kBlock / n2;
 };
 
-// Cells per chunk in x, y, z for degree K (n^2 lanes per cell, at most 256 lanes), and
-// chunks per brick along x.
+// Cells per chunk in x, y, z for degree K, chunks per brick along x, and the lane layout:
+// wave = true places every cell's n^2 lanes inside one wavefront (64 / n^2 cells per
+// wavefront, four wavefronts per work-group), so the phases of a cell need no work-group
+// barrier; wave = false packs the cells densely over the work-group (cells may straddle
+// wavefronts; required for n^2 > 64).
 template <int K> struct Brick;
-template <> struct Brick<1> { static constexpr int x = 4, y = 4, z = 4, chunks = 1; };
-template <> struct Brick<2> { static constexpr int x = 3, y = 3, z = 3, chunks = 1; };
-template <> struct Brick<3> { static constexpr int x = 4, y = 2, z = 2, chunks = 2; };
-template <> struct Brick<4> { static constexpr int x = 2, y = 2, z = 2, chunks = 2; };
-template <> struct Brick<5> { static constexpr int x = 3, y = 2, z = 1, chunks = 2; };
-template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; };
-template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; };
-template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2; };
+template <> struct Brick<1> { static constexpr int x = 4, y = 4, z = 4, chunks = 1; static constexpr bool wave = true; };
+template <> struct Brick<2> { static constexpr int x = 3, y = 3, z = 3, chunks = 1; static constexpr bool wave = true; };
+template <> struct Brick<3> { static constexpr int x = 4, y = 2, z = 2, chunks = 2; static constexpr bool wave = true; };
+template <> struct Brick<4> { static constexpr int x = 2, y = 2, z = 2, chunks = 4; static constexpr bool wave = true; };
+template <> struct Brick<5> { static constexpr int x = 3, y = 2, z = 1, chunks = 2; static constexpr bool wave = false; };
+template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; static constexpr bool wave = true; };
+template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; static constexpr bool wave = true; };
+template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2; static constexpr bool wave = false; };
+
+// Lane -> (cell slot, lane within the cell) of a work-group of kBlock lanes.
+template <int N2, bool WAVE>
+struct LaneMap {
+  int slot, p;
+  bool used;   // lane belongs to a cell slot below `slots`
+  __device__ __forceinline__ LaneMap(int t, int slots) {
+    if constexpr (WAVE) {
+      constexpr int CPW = 64 / N2;
+      const int w = t / 64, ln = t % 64, s = ln / N2;
+      slot = w * CPW + s;
+      p = ln - s * N2;
+      used = s < CPW && slot < slots;
+    } else {
+      slot = t / N2;
+      p = t - slot * N2;
+      used = slot < slots;
+    }
+  }
+};
 
 struct CellCtx {
   int i0, i1;        // lane coordinates within the cell
@@ -80,25 +103,46 @@ __device__ __forceinline__ bool z_bnd(const CellCtx &c, int l) {
   return c.bxy || (c.dirichlet && on_boundary(c.cz * c.K + l, c.N1));
 }
 
+// The lane's z-line of src (Dirichlet DoFs and inactive lanes read as zero: the columns of
+// the Dirichlet DoFs are eliminated).
+template <int N, typename T>
+__device__ __forceinline__ void gather_zline(const CellCtx &cc, const T *__restrict__ src, T (&u)[N]) {
+#pragma unroll
+  for (int l = 0; l < N; ++l) u[l] = (cc.active && !z_bnd(cc, l)) ? src[cc.base + cc.plane * l] : T(0);
+}
+
+// The metric of the lane's z-line of Gauss points (layout [6][q] per cell).
+template <int N, typename T>
+__device__ __forceinline__ void load_metric(bool active, const T *__restrict__ gm, int p, T (&g)[6][N]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int l = 0; l < N; ++l) g[c][l] = active ? gm[c * N * N * N + l * N * N + p] : T(0);
+}
+
+struct NoOp {
+  __device__ void operator()() const {}
+};
+
 // ---------------------------------------------------------------------------------------
 // Cartesian cell: constant Jacobian h I, so with exact Gauss quadrature the element
 // operator of eq. (mf_eval) factors into the Kronecker sum
 //   A_e = scale (K (x) M (x) M + M (x) K (x) M + M (x) M (x) K),  scale = kappa_e h,
 // of the reference 1D mass M and stiffness K of the GLL basis (the same numbers as the
 // quadrature form, re-associated).  Seven 1D applications per line set.
-// Buffers A..D: n^3 each.  TXS == 0: y_e ends in A; TXS > 0: y_e is added (LDS atomics)
-// into `tile` (row stride TXS, plane stride TXS * TYS, this cell's origin at `tile`).
-// Contains 3 work-group barriers.
-template <int K, typename T, int TXS = 0, int TYS = 0>
-__device__ __forceinline__ void cart_cell(const CellCtx &cc, const T *__restrict__ src, T scale, T *A, T *B,
-                                          T *C, T *D, const EOTab<K + 1, T> &eo, T *tile = nullptr) {
+// u: the lane's gathered z-line.  Buffers A..D: n^3 each.  TXS == 0: y_e ends in A;
+// TXS > 0: y_e is added (LDS atomics) into `tile` (row stride TXS, plane stride
+// TXS * TYS, this cell's origin at `tile`).  after_gather() runs once u is consumed (it may
+// overwrite u with the next cell's line).  Contains 3 cell barriers.
+template <int K, typename T, int TXS = 0, int TYS = 0, bool WL = false, class AfterGather = NoOp>
+__device__ __forceinline__ void cart_cell(const CellCtx &cc, const T (&u)[K + 1], T scale, T *A, T *B, T *C,
+                                          T *D, const EOTab<K + 1, T> &eo, double *tile = nullptr,
+                                          AfterGather after_gather = {}) {
   constexpr int n = K + 1, n2 = n * n;
   const int i0 = cc.i0, i1 = cc.i1, p = i0 + n * i1;
-  // z-lines (x = i0, y = i1): gather, then M and K along z
+  // z-lines (x = i0, y = i1): M and K along z
   if (cc.inblk) {
-    T u[n], a[n], b[n];
-#pragma unroll
-    for (int l = 0; l < n; ++l) u[l] = (cc.active && !z_bnd(cc, l)) ? src[cc.base + cc.plane * l] : T(0);
+    T a[n], b[n];
     eo_apply<n, 1>(eo.M, u, a);
     eo_apply<n, 1>(eo.K, u, b);
 #pragma unroll
@@ -107,7 +151,8 @@ __device__ __forceinline__ void cart_cell(const CellCtx &cc, const T *__restrict
       B[q * n2 + p] = b[q];
     }
   }
-  __syncthreads();
+  after_gather();
+  cell_sync<WL>();
   // y-lines (x = i0, z = i1): P = M_y (M_z u), S = K_y (M_z u) + M_y (K_z u)
   if (cc.inblk) {
     T a1[n], a2[n], pp[n], s1[n], s2[n];
@@ -125,7 +170,7 @@ __device__ __forceinline__ void cart_cell(const CellCtx &cc, const T *__restrict
       D[i1 * n2 + q * n + i0] = s1[q] + s2[q];
     }
   }
-  __syncthreads();
+  cell_sync<WL>();
   // x-lines (y = i0, z = i1): y = scale (K_x P + M_x S)
   if (cc.inblk) {
     T pa[n], sa[n], y1[n], y2[n];
@@ -140,12 +185,12 @@ __device__ __forceinline__ void cart_cell(const CellCtx &cc, const T *__restrict
     for (int q = 0; q < n; ++q) {
       const T y = (y1[q] + y2[q]) * scale;
       if constexpr (TXS > 0)
-        lds_add(tile + i1 * (TXS * TYS) + i0 * TXS + q, y);
+        lds_add(tile + i1 * (TXS * TYS) + i0 * TXS + q, double(y));
       else
         A[i1 * n2 + i0 * n + q] = y;
     }
   }
-  __syncthreads();
+  cell_sync<WL>();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -154,30 +199,28 @@ __device__ __forceinline__ void cart_cell(const CellCtx &cc, const T *__restrict
 // from HBM, layout [cell][6][q]; kappa applied on the fly).  Collocation form of sum
 // factorization: values at the Gauss points v = (S (x) S (x) S) u, reference gradient by
 // the Gauss-point collocation derivative D per direction, q = kappa G grad v, then the
-// transposed sequence.  Buffers A..C; y_e ends in A (TXS == 0) or is added into `tile` as
-// for cart_cell.  Contains 9 work-group barriers.
-template <int K, typename T, int TXS = 0, int TYS = 0>
-__device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restrict__ src, const T *gm, T kap,
-                                            T *A, T *B, T *C, const EOTab<K + 1, T> &eo,
-                                            T *tile = nullptr) {
-  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n;
+// transposed sequence.  u: the lane's gathered z-line; g: the metric of the lane's z-line
+// of Gauss points.  Buffers A..C; y_e ends in A (TXS == 0) or is added into `tile` as for
+// cart_cell.  after_gather() runs once u is consumed, after_metric() once g and kap are
+// (both may overwrite them with the next cell's operands, so that those loads are in
+// flight during the rest of this cell).  Contains 9 cell barriers.
+template <int K, typename T, int TXS = 0, int TYS = 0, bool WL = false, class AfterGather = NoOp,
+          class AfterMetric = NoOp>
+__device__ __forceinline__ void curved_cell(const CellCtx &cc, const T (&u)[K + 1], const T (&g)[6][K + 1],
+                                            const T &kap, T *A, T *B, T *C, const EOTab<K + 1, T> &eo,
+                                            double *tile = nullptr, AfterGather after_gather = {},
+                                            AfterMetric after_metric = {}) {
+  constexpr int n = K + 1, n2 = n * n;
   const int i0 = cc.i0, i1 = cc.i1, p = i0 + n * i1;
-  T g[6][n];
-  // F1: z-lines (x = i0, y = i1): gather, S along z; the metric loads are issued here so
-  // that they are in flight during the next phases (gm is a valid cell for every lane)
+  // F1: z-lines (x = i0, y = i1): S along z
   if (cc.inblk) {
-    T u[n], t[n];
-#pragma unroll
-    for (int l = 0; l < n; ++l) u[l] = (cc.active && !z_bnd(cc, l)) ? src[cc.base + cc.plane * l] : T(0);
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-#pragma unroll
-      for (int l = 0; l < n; ++l) g[c][l] = gm[c * n3 + l * n2 + p];
+    T t[n];
     eo_apply<n, 1>(eo.S, u, t);
 #pragma unroll
     for (int q = 0; q < n; ++q) A[q * n2 + p] = t[q];
   }
-  __syncthreads();
+  after_gather();
+  cell_sync<WL>();
   // F2: y-lines (x = i0, z = i1): S along y
   if (cc.inblk) {
     T r[n], t[n];
@@ -187,7 +230,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
 #pragma unroll
     for (int q = 0; q < n; ++q) B[i1 * n2 + q * n + i0] = t[q];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // F3: x-lines (y = i0, z = i1): S along x -> values v at the Gauss points; D -> dv/dx
   if (cc.inblk) {
     T r[n], v[n], d[n];
@@ -201,7 +244,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
       C[i1 * n2 + i0 * n + q] = d[q];
     }
   }
-  __syncthreads();
+  cell_sync<WL>();
   // F4: y-lines (x = i0, z = i1): D along y -> dv/dy
   if (cc.inblk) {
     T r[n], d[n];
@@ -211,7 +254,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
 #pragma unroll
     for (int q = 0; q < n; ++q) B[i1 * n2 + q * n + i0] = d[q];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // F5 + B1: z-lines (x = i0, y = i1): D along z -> dv/dz; quadrature-point operation;
   // transposed derivative along z.  Each lane rewrites only its own z-line.
   if (cc.inblk) {
@@ -235,7 +278,8 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
       B[l * n2 + p] = fy[l];
     }
   }
-  __syncthreads();
+  after_metric();
+  cell_sync<WL>();
   // B2: y-lines (x = i0, z = i1): acc += D^T along y of fy
   if (cc.inblk) {
     T f[n], d[n];
@@ -245,7 +289,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
 #pragma unroll
     for (int b = 0; b < n; ++b) A[i1 * n2 + b * n + i0] += d[b];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // B3: x-lines (y = i0, z = i1): acc += D^T along x of fx; S^T along x
   if (cc.inblk) {
     T f[n], d[n], acc[n], w[n];
@@ -258,7 +302,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
 #pragma unroll
     for (int i = 0; i < n; ++i) B[i1 * n2 + i0 * n + i] = w[i];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // B4: y-lines (x = i0, z = i1): S^T along y
   if (cc.inblk) {
     T r[n], w[n];
@@ -268,7 +312,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
 #pragma unroll
     for (int i = 0; i < n; ++i) A[i1 * n2 + i * n + i0] = w[i];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // B5: z-lines (x = i0, y = i1): S^T along z; y_e back into A (own z-line only) or into
   // the tile
   if (cc.inblk) {
@@ -279,12 +323,12 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T *__restri
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       if constexpr (TXS > 0)
-        lds_add(tile + i * (TXS * TYS) + i1 * TXS + i0, w[i]);
+        lds_add(tile + i * (TXS * TYS) + i1 * TXS + i0, double(w[i]));
       else
         A[i * n2 + p] = w[i];
     }
   }
-  __syncthreads();
+  cell_sync<WL>();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -311,6 +355,9 @@ __device__ __forceinline__ int halo_index(int X, int Y, int Z, int MX, int MY, i
   return X == MX ? fx : (Y == MY ? fy : fz);
 }
 
+// dst = A src for CG Q_K, one brick per work-group.  The work-group walks the chunks of its
+// brick; every lane holds the src line (and, on curved meshes, the metric and kappa) of its
+// cell of the next chunk in registers, loaded while the current chunk is computed.
 template <int K, typename T, bool CURVED>
 __global__ void __launch_bounds__(kBlock)
 apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ halo,
@@ -320,68 +367,148 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   using Bk = Brick<K>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
   constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ, NCH = Bk::chunks;
-  static_assert(CPB * n2 <= kBlock, "chunk does not fit the work-group");
+  constexpr bool WL = Bk::wave;
+  static_assert(WL ? (n2 <= 64 && CPB <= (kBlock / 64) * (64 / n2)) : CPB * n2 <= kBlock,
+                "chunk does not fit the work-group");
   constexpr int MX = NCH * CX * K, MY = BY * K, MZ = BZ * K;   // brick extent in DoF intervals
   constexpr int TX = MX + 1, TY = MY + 1, TZ = MZ + 1;
   constexpr int NBUF = CURVED ? 3 : 4;
   constexpr int ITEMS = TX * TY * TZ, ITERS = (ITEMS + kBlock - 1) / kBlock;
   __shared__ T sm[NBUF][CPB * n3];
-  __shared__ T tile[ITEMS];
+  __shared__ double tile[ITEMS];   // FP64 accumulation also for T = float (ds_add_f32 is slow)
 
-  const int nb = bg.nbx * bg.nby * bg.nbz;
-  const int brick = xcd_block(blockIdx.x, nb);
+  const int brick = xcd_block(blockIdx.x, bg.nbx * bg.nby * bg.nbz);
   const int bx = brick % bg.nbx, by = (brick / bg.nbx) % bg.nby, bz = brick / (bg.nbx * bg.nby);
-  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2;
+  const int t = threadIdx.x;
+  const LaneMap<n2, WL> lm(t, CPB);
+  const int lc = lm.used ? lm.slot : 0, p = lm.p;
   const int lx = lc % CX, ly = (lc / CX) % BY, lz = lc / (CX * BY);
-  const bool inblk = lc < CPB;
+  const bool inblk = lm.used;
   const int Nc = bg.Nc, N1 = bg.N1;
   const int cx0 = bx * NCH * CX, cy = by * BY + ly, cz = bz * BZ + lz;
   const int nchunks = min(NCH, (Nc - cx0 + CX - 1) / CX);
-  const int slot = inblk ? lc : 0;
-  T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[2] + slot * n3;
+  T *A = sm[0] + lc * n3, *B = sm[1] + lc * n3, *C = sm[2] + lc * n3;
+
+  // the lane's cell in chunk j (inactive past the brick's last chunk)
+  auto cell_at = [&](int j, CellCtx &cc, int64_t &cell) {
+    const int cx = cx0 + j * CX + lx;
+    const bool active = inblk && j < nchunks && cx < Nc && cy < Nc && cz < Nc;
+    cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
+    cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, bg.dirichlet);
+  };
 
 #pragma unroll
   for (int it = 0; it < ITERS; ++it) {
     const int i = t + it * kBlock;
-    if (ITEMS % kBlock == 0 || i < ITEMS) tile[i] = T(0);
+    if (ITEMS % kBlock == 0 || i < ITEMS) tile[i] = 0.0;
   }
-  // chunks of CX x BY x BZ cells; each cell adds its local result into the brick tile
-  // (the cell functions contain barriers before their first tile access)
-  for (int j = 0; j < nchunks; ++j) {
-    const int cx = cx0 + j * CX + lx;
-    const bool active = inblk && cx < Nc && cy < Nc && cz < Nc;
-    const int64_t cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
-    const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, bg.dirichlet);
-    T *ctile = tile + (lz * K) * (TX * TY) + (ly * K) * TX + (j * CX + lx) * K;
+  __syncthreads();
+
+  CellCtx cc;
+  int64_t cell;
+  cell_at(0, cc, cell);
+  T u[n];
+  T g[6][CURVED ? n : 1];
+  gather_zline(cc, src, u);
+  if constexpr (CURVED) load_metric(cc.active, metric + cell * (6 * n3), p, g);
+  T kap = cc.active ? kappa[cell] : T(0);
+
+#pragma unroll
+  for (int j = 0; j < NCH; ++j) {
+    if (j >= nchunks) break;
+    CellCtx cn;
+    int64_t celln;
+    cell_at(j + 1, cn, celln);
+    double *ctile = tile + (lz * K) * (TX * TY) + (ly * K) * TX + (j * CX + lx) * K;
     if constexpr (CURVED) {
-      const T kap = active ? kappa[cell] : T(0);
-      curved_cell<K, T, TX, TY>(cc, src, metric + cell * (6 * n3), kap, A, B, C, eo, ctile);
+      curved_cell<K, T, TX, TY, WL>(
+          cc, u, g, kap, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
+          [&] {
+            load_metric(cn.active, metric + celln * (6 * n3), p, g);
+            kap = cn.active ? kappa[celln] : T(0);
+          });
     } else {
-      T *D = sm[NBUF - 1] + slot * n3;
-      const T scale = active ? kappa[cell] * h : T(0);
-      cart_cell<K, T, TX, TY>(cc, src, scale, A, B, C, D, eo, ctile);
+      T *D = sm[NBUF - 1] + lc * n3;
+      T kn = 0;
+      cart_cell<K, T, TX, TY, WL>(cc, u, kap * h, A, B, C, D, eo, ctile, [&] {
+        gather_zline(cn, src, u);
+        kn = cn.active ? kappa[celln] : T(0);
+      });
+      kap = kn;
     }
+    cc = cn;
+    cell = celln;
   }
-  // owned DoFs -> dst (Dirichlet: identity row), upper faces of inner bricks -> halo record
+  __syncthreads();
+
+  // Stores.  Tile items with X < MX, Y < MY, Z < MZ are owned by this brick; items on the
+  // upper faces are owned by a neighbouring brick (-> halo record) unless the brick is the
+  // last one in every direction in which the item lies on its upper face (-> dst).
+  // Dirichlet DoFs get the identity-row value src.
   const bool lastx = bx == bg.nbx - 1, lasty = by == bg.nby - 1, lastz = bz == bg.nbz - 1;
   const int64_t plane = int64_t(N1) * N1;
   const int gx0 = cx0 * K, gy0 = by * MY, gz0 = bz * MZ;
-  T *hrec = halo + int64_t(brick) * halo_size(MX, MY, MZ);
+  const int64_t gbase = gx0 + int64_t(N1) * gy0 + plane * gz0;
+  // interior bricks without Dirichlet DoFs and without cut-off cells need no per-item tests
+  const bool plain = gx0 + MX < N1 - 1 && gy0 + MY < N1 - 1 && gz0 + MZ < N1 - 1 &&
+                     !(bg.dirichlet && (gx0 == 0 || gy0 == 0 || gz0 == 0));
+  constexpr int OWN = MX * MY * MZ, ITO = (OWN + kBlock - 1) / kBlock;
 #pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
-    const int i0 = t + it * kBlock;
-    const bool in_tile = ITEMS % kBlock == 0 || i0 < ITEMS;
-    const int i = in_tile ? i0 : 0;
-    const int X = i % TX, Y = (i / TX) % TY, Z = i / (TX * TY);
-    const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
-    const bool valid = in_tile && gx < N1 && gy < N1 && gz < N1;
-    const bool is_halo = (X == MX && !lastx) || (Y == MY && !lasty) || (Z == MZ && !lastz);
-    const int64_t g = gx + int64_t(N1) * gy + plane * gz;
-    const bool bnd = bg.dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1));
-    T *addr = is_halo ? hrec + halo_index(X, Y, Z, MX, MY, MZ) : dst + g;
-    const T v = tile[i];
-    const T out = (valid && bnd && !is_halo) ? src[g] : v;
-    if (valid) *addr = out;
+  for (int it = 0; it < ITO; ++it) {
+    const int i = t + it * kBlock;
+    if (OWN % kBlock == 0 || i < OWN) {
+      const int X = i % MX, Y = (i / MX) % MY, Z = i / (MX * MY);
+      const int64_t gi = gbase + (X + N1 * Y) + plane * Z;
+      const T v = T(tile[X + TX * (Y + TY * Z)]);
+      if (plain) {
+        dst[gi] = v;
+      } else {
+        const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
+        if (gx < N1 && gy < N1 && gz < N1) {
+          const bool bnd =
+              bg.dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1));
+          dst[gi] = bnd ? src[gi] : v;
+        }
+      }
+    }
+  }
+  constexpr int HS = (MY + 1) * (MZ + 1) + MX * (MZ + 1) + MX * MY, ITH = (HS + kBlock - 1) / kBlock;
+  T *hrec = halo + int64_t(brick) * HS;
+#pragma unroll
+  for (int it = 0; it < ITH; ++it) {
+    const int i = t + it * kBlock;
+    if (HS % kBlock == 0 || i < HS) {
+      // decode the record index (layout of halo_index)
+      int X, Y, Z;
+      if (i < (MY + 1) * (MZ + 1)) {
+        X = MX;
+        Y = i % (MY + 1);
+        Z = i / (MY + 1);
+      } else if (i < (MY + 1) * (MZ + 1) + MX * (MZ + 1)) {
+        const int q = i - (MY + 1) * (MZ + 1);
+        X = q % MX;
+        Y = MY;
+        Z = q / MX;
+      } else {
+        const int q = i - (MY + 1) * (MZ + 1) - MX * (MZ + 1);
+        X = q % MX;
+        Y = q / MX;
+        Z = MZ;
+      }
+      const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
+      if (gx < N1 && gy < N1 && gz < N1) {
+        const T v = T(tile[X + TX * (Y + TY * Z)]);
+        const bool is_halo = (X == MX && !lastx) || (Y == MY && !lasty) || (Z == MZ && !lastz);
+        if (is_halo) {
+          hrec[i] = v;
+        } else {
+          const int64_t gi = gbase + (X + N1 * Y) + plane * Z;
+          const bool bnd =
+              bg.dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1));
+          dst[gi] = bnd ? src[gi] : v;
+        }
+      }
+    }
   }
 }
 
@@ -469,11 +596,15 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
   const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, dirichlet);
   const int slot = inblk ? lc : 0;
   T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[2] + slot * n3;
+  T ul[n];
+  gather_zline(cc, u, ul);
   if constexpr (CURVED) {
-    curved_cell<K, T>(cc, u, metric + (active ? cell : 0) * (6 * n3), T(1), A, B, C, eo);
+    T g[6][n];
+    load_metric(active, metric + (active ? cell : 0) * (6 * n3), p, g);
+    curved_cell<K, T>(cc, ul, g, T(1), A, B, C, eo);
   } else {
     T *D = sm[NBUF - 1] + slot * n3;
-    cart_cell<K, T>(cc, u, active ? h : T(0), A, B, C, D, eo);
+    cart_cell<K, T>(cc, ul, active ? h : T(0), A, B, C, D, eo);
   }
   T partial = 0;
   if (active) {
