@@ -14,15 +14,20 @@
  *   - additions: the V-cycle may run in FP32 inside the FP64 outer CG; an adjoint
  *     solve and a per-cell gradient with respect to a cellwise kappa.
  *
- * Mesh: the unit cube [0,1]^3 with N_c^3 cells (lexicographic, x fastest), either
- * Cartesian or deformed by x + a sin(pi x) sin(pi y) sin(pi z) (1,1,1) through the
- * isoparametric Q_k map at the Gauss-Lobatto support points (Sec. 2).
+ * Mesh: the cube [lo, lo + len]^3 (default the unit cube) with N_c^3 cells
+ * (lexicographic, x fastest), either Cartesian or, on the unit cube, deformed by
+ * x + a sin(pi x) sin(pi y) sin(pi z) (1,1,1) through the isoparametric Q_k map at the
+ * Gauss-Lobatto support points (Sec. 2).
+ *
+ * Boundary conditions: Dirichlet on all faces, Neumann on all faces (operator only), or
+ * mixed as in the smooth-solution example of Sec. 5: Neumann on the faces x_e = lo and
+ * Dirichlet on the faces x_e = lo + len.
  *
  * Vectors:
  *   - CG: full-length (k N_c + 1)^3 vector, lexicographic on the grid of per-cell
- *     Gauss-Lobatto positions, x fastest; boundary DoFs included.  With Dirichlet
- *     conditions the operator is the identity on boundary DoFs and their columns
- *     are eliminated (symmetric positive definite on the whole space).
+ *     Gauss-Lobatto positions, x fastest; boundary DoFs included.  The operator is the
+ *     identity on the DoFs of Dirichlet faces and their columns are eliminated
+ *     (symmetric positive definite on the whole space when some face is Dirichlet).
  *   - DG (SIPG): cell-major, N_c^3 (k+1)^3 values, local index i + n j + n^2 l
  *     (n = k+1), basis = Lagrange polynomials in the Gauss-Legendre points.
  *
@@ -59,6 +64,7 @@ extern "C" {
 #define MFL_GEOM_CURVED 1
 #define MFL_BC_DIRICHLET 0
 #define MFL_BC_NEUMANN 1
+#define MFL_BC_MIXED 2        /* Neumann at x_e = lo, Dirichlet at x_e = lo + len (Sec. 5) */
 #define MFL_F64 0
 #define MFL_F32 1
 
@@ -69,7 +75,7 @@ typedef struct mfl_params {
   int disc;               /* MFL_DISC_CG or MFL_DISC_SIPG */
   int geometry;           /* MFL_GEOM_CARTESIAN or MFL_GEOM_CURVED (CG only) */
   double curve_amp;       /* a of the deformation (default 0.1; ignored when Cartesian) */
-  int bc;                 /* MFL_BC_DIRICHLET (homogeneous) or MFL_BC_NEUMANN (apply only) */
+  int bc;                 /* MFL_BC_DIRICHLET, MFL_BC_MIXED, or MFL_BC_NEUMANN (apply only) */
   double penalty_factor;  /* SIPG: sigma = penalty_factor (k+1)^2 / h (paper: 3 = d) */
   int cheb_degree;        /* smoother degree (Sec. 4.1: 5) */
   double cheb_lo;         /* lower end of the smoothing interval / lambda_max (0.06) */
@@ -78,6 +84,8 @@ typedef struct mfl_params {
   double coarse_tol;      /* a-priori error bound of the coarse Chebyshev solver (1e-3) */
   int mg_precision;       /* MFL_F64 or MFL_F32: arithmetic of the V-cycle */
   int build_mg;           /* 0: finest-level operator only; 1: multigrid hierarchy */
+  double domain_lo;       /* the mesh covers [domain_lo, domain_lo + domain_len]^3 (0) */
+  double domain_len;      /* (1; curved meshes need the unit cube) */
 } mfl_params;
 
 typedef struct mfl_context *mfl_handle;
@@ -152,6 +160,18 @@ int mfl_rhs_sine(mfl_handle h, double *b, void *stream);
 /* Adjoint solve A lambda = dJdu with the same operator and preconditioner (A is symmetric);
  * the Dirichlet entries of the right-hand side are taken as zero.  Same outputs and errors
  * as mfl_pcg_solve. */
+/* Right-hand side of the smooth-solution example (Sec. 5, eq. pois_analytic: a sum of
+ * three Gaussians of width 1/5 centred at (-0.5,0.5,0.25), (-0.6,-0.5,-0.125),
+ * (0.5,-0.5,0.5)) on the handle's Cartesian CG mesh and boundary conditions:
+ *   b_i = int f phi_i + int_{Neumann faces} (grad u . n) phi_i - (A0 x0)_i  off the
+ *         Dirichlet faces, b_i = x0_i on them,
+ * f = -Laplace u with k+1 Gauss points per direction, x0 = u interpolated at the DoFs of
+ * the Dirichlet faces (0 elsewhere), A0 = the operator without boundary conditions.  The
+ * solution of A x = b then carries the Dirichlet data.  b: device, n_dofs doubles.
+ * Uses the handle's work vectors (not concurrently with a solve on the same handle).
+ * Errors: MFL_EUNSUPPORTED for SIPG or curved meshes.  Asynchronous. */
+int mfl_rhs_gaussians(mfl_handle h, double *b, void *stream);
+
 int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double rtol, int maxit,
                       int *iters, double *final_rel_res, void *stream);
 

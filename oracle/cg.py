@@ -77,8 +77,9 @@ def element_matrices(box, kappa=None, cells=None, n_quad=None):
 
 
 def assemble(box, kappa=None, bc="dirichlet", n_quad=None):
-    """Global CSR matrix.  bc='dirichlet': identity rows/columns on the boundary;
-    bc='neumann': the plain assembled matrix (homogeneous Neumann everywhere)."""
+    """Global CSR matrix.  Identity rows/columns on the DoFs of the Dirichlet faces of
+    `bc` ('dirichlet': all faces, 'mixed': the upper faces, or a face mask); 'neumann':
+    the plain assembled matrix (natural conditions everywhere)."""
     Ae = element_matrices(box, kappa, n_quad=n_quad)
     dofs = box.cell_dofs()
     n3 = box.n ** 3
@@ -86,12 +87,11 @@ def assemble(box, kappa=None, bc="dirichlet", n_quad=None):
     cols = np.tile(dofs, (1, n3)).ravel()
     A = sp.coo_matrix((Ae.ravel(), (rows, cols)), shape=(box.n_dofs, box.n_dofs)).tocsr()
     A.sum_duplicates()
-    if bc == "neumann":
+    dmask = box.boundary_mask(bc)
+    if not dmask.any():
         return A
-    if bc != "dirichlet":
-        raise ValueError(bc)
-    keep = sp.diags((~box.boundary_mask()).astype(np.float64))
-    bnd = sp.diags(box.boundary_mask().astype(np.float64))
+    keep = sp.diags((~dmask).astype(np.float64))
+    bnd = sp.diags(dmask.astype(np.float64))
     return (keep @ A @ keep + bnd).tocsr()
 
 
@@ -108,15 +108,15 @@ def cells_of_dof(box, dof):
     return [cx + Nc * (cy + Nc * cz) for cz in ranges[2] for cy in ranges[1] for cx in ranges[0]]
 
 
-def apply_rows(box, u, rows, kappa=None):
-    """(A u)[rows] with the Dirichlet operator, element by element.
+def apply_rows(box, u, rows, kappa=None, bc="dirichlet"):
+    """(A u)[rows] with the operator of `assemble` (same bc), element by element.
 
     Used at sizes where the CSR matrix does not fit: each requested row is the
     sum over the cells containing that DoF of the corresponding row of A^e times
-    the cell's (boundary-zeroed) values.
+    the cell's (Dirichlet-zeroed) values.
     """
     rows = np.asarray(rows)
-    bmask = box.boundary_mask()
+    bmask = box.boundary_mask(bc)
     cell_lists = [cells_of_dof(box, int(r)) for r in rows]
     uniq = np.unique(np.concatenate([np.asarray(c) for c in cell_lists]))
     Ae = element_matrices(box, kappa, cells=uniq)
@@ -171,6 +171,22 @@ def rhs(box, f=sine_forcing, n_quad=None, zero_boundary=True):
 def interpolate(box, fn):
     """Nodal interpolant: u_i = fn(x_i) at the physical DoF positions."""
     return fn(box.dof_points())
+
+
+def l2_norm(box, fn, extra_points=2):
+    """|| fn ||_{L2} over the mesh with k+1+extra_points Gauss points per direction."""
+    xq, wq = gauss_legendre(box.n + extra_points)
+    val, grad = reference_tables(box.gll, xq)
+    w3 = tensor_weights(wq)
+    s2 = 0.0
+    chunk = 2048
+    for s in range(0, box.n_cells, chunk):
+        cs = np.arange(s, min(s + chunk, box.n_cells))
+        X = box.cell_node_coords(cs)
+        det = np.linalg.det(cell_geometry(X, grad))
+        xphys = np.einsum("qi,eia->eqa", val, X)
+        s2 += np.sum(w3[None, :] * det * fn(xphys) ** 2)
+    return float(np.sqrt(s2))
 
 
 def l2_error(box, u, exact=sine_solution, extra_points=2):

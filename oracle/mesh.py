@@ -1,4 +1,4 @@
-"""Structured hexahedral meshes of the unit cube and their degree-k node sets.
+"""Structured hexahedral meshes of a cube and their degree-k node sets.
 
 Section 2: elements are images of the reference cube under a polynomial map of
 degree k whose support points are the Gauss-Lobatto nodes, placed by a manifold
@@ -7,7 +7,15 @@ description.  Here the manifold is the box [0,1]^3 deformed by
     Phi(X) = X + a * sin(pi X) sin(pi Y) sin(pi Z) * (1, 1, 1),
 
 the same scalar added to each coordinate (a = 0: Cartesian mesh).  The map is the
-identity on the boundary of the cube, so the physical domain stays [0,1]^3.
+identity on the boundary of the cube, so the physical domain stays [0,1]^3.  A
+Cartesian box may also cover [lo, lo + length]^3 (the paper's smooth-solution example
+uses (-1, 1)^3).
+
+Boundary conditions are described per face by a mask: bit 0 set means the three
+lower faces (x_e = lo) carry Dirichlet conditions, bit 1 the three upper faces
+(x_e = lo + length); faces without Dirichlet conditions carry Neumann conditions.
+'dirichlet' = 3, 'neumann' = 0, 'mixed' = 2 (the smooth-solution example: Neumann at
+x_e = -1, Dirichlet at x_e = +1).
 
 Numbering (shared with nothing; stated so that tests can compare layouts):
 * cells lexicographic, x fastest: c = cx + Nc (cy + Nc cz);
@@ -20,17 +28,28 @@ import numpy as np
 from .basis import gauss_lobatto
 
 
-class Box:
-    """N_c^3 cells of the unit cube carrying the continuous Q_k space."""
+BC_MASKS = {"dirichlet": 3, "neumann": 0, "mixed": 2}
 
-    def __init__(self, cells_per_dim, degree, curve_amp=0.0):
+
+def bc_mask(bc):
+    return BC_MASKS[bc] if isinstance(bc, str) else int(bc)
+
+
+class Box:
+    """N_c^3 cells of a cube carrying the continuous Q_k space."""
+
+    def __init__(self, cells_per_dim, degree, curve_amp=0.0, lo=0.0, length=1.0):
         if cells_per_dim < 1 or degree < 1:
             raise ValueError("need at least one cell and degree >= 1")
+        if curve_amp != 0.0 and (lo != 0.0 or length != 1.0):
+            raise ValueError("the curved map is defined on the unit cube only")
         self.Nc = int(cells_per_dim)
         self.k = int(degree)
         self.n = self.k + 1
         self.N1 = self.k * self.Nc + 1
-        self.h = 1.0 / self.Nc
+        self.lo = float(lo)
+        self.length = float(length)
+        self.h = self.length / self.Nc
         self.a = float(curve_amp)
         self.n_cells = self.Nc ** 3
         self.n_dofs = self.N1 ** 3
@@ -54,9 +73,11 @@ class Box:
         gz = cz[:, None] * k + loc_z[None, :]
         return gx + N1 * (gy + N1 * gz)
 
-    def boundary_mask(self):
+    def boundary_mask(self, bc="dirichlet"):
+        """DoFs on faces with Dirichlet conditions (bc: name or face mask)."""
+        m = bc_mask(bc)
         g = np.arange(self.N1)
-        b1 = (g == 0) | (g == self.N1 - 1)
+        b1 = ((g == 0) & bool(m & 1)) | ((g == self.N1 - 1) & bool(m & 2))
         bz, by, bx = np.meshgrid(b1, b1, b1, indexing="ij")
         return (bx | by | bz).ravel()
 
@@ -64,7 +85,7 @@ class Box:
         """Reference (undeformed) coordinate of each of the N1 grid lines."""
         g = np.arange(self.N1)
         c = np.minimum(g // self.k, self.Nc - 1)
-        return (c + self.gll[g - c * self.k]) * self.h
+        return self.lo + (c + self.gll[g - c * self.k]) * self.h
 
     # ---- geometry -------------------------------------------------------
     def deform(self, X):
@@ -87,7 +108,7 @@ class Box:
         lx = np.tile(self.gll, n * n)
         ly = np.tile(np.repeat(self.gll, n), n)
         lz = np.repeat(self.gll, n * n)
-        X = np.stack([(cx[:, None] + lx[None, :]) * self.h,
-                      (cy[:, None] + ly[None, :]) * self.h,
-                      (cz[:, None] + lz[None, :]) * self.h], axis=-1)
+        X = np.stack([self.lo + (cx[:, None] + lx[None, :]) * self.h,
+                      self.lo + (cy[:, None] + ly[None, :]) * self.h,
+                      self.lo + (cz[:, None] + lz[None, :]) * self.h], axis=-1)
         return self.deform(X)

@@ -50,12 +50,12 @@ def prolongation_1d(coarse, fine):
     return P
 
 
-def prolongation(coarse, fine):
+def prolongation(coarse, fine, bc="dirichlet"):
     """3D embedding with Dirichlet rows (fine) and columns (coarse) removed."""
     P1 = sp.csr_matrix(prolongation_1d(coarse, fine))
     P = sp.kron(P1, sp.kron(P1, P1)).tocsr()
-    keep_f = sp.diags((~fine.boundary_mask()).astype(np.float64))
-    keep_c = sp.diags((~coarse.boundary_mask()).astype(np.float64))
+    keep_f = sp.diags((~fine.boundary_mask(bc)).astype(np.float64))
+    keep_c = sp.diags((~coarse.boundary_mask(bc)).astype(np.float64))
     return (keep_f @ P @ keep_c).tocsr()
 
 
@@ -139,10 +139,12 @@ def coarse_steps(lmin, lmax, eps=1e-3):
 
 
 class Multigrid:
-    """Level hierarchy, smoother data and V(1,1) cycle for the Dirichlet CG operator."""
+    """Level hierarchy, smoother data and V(1,1) cycle for the CG operator with Dirichlet
+    conditions on the faces of `bc` ('dirichlet': all, 'mixed': the upper faces)."""
 
     def __init__(self, fine_cells, degree, kappa=None, curve_amp=0.0, min_cells=2,
-                 cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_eps=1e-3):
+                 cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_eps=1e-3,
+                 bc="dirichlet", lo=0.0, length=1.0):
         self.cheb_updates = cheb_degree + 1
         sizes = []
         Nc = fine_cells
@@ -159,22 +161,22 @@ class Multigrid:
         kappas = kappas[::-1]
         self.levels = []
         for l, Nc in enumerate(sizes):
-            box = Box(Nc, degree, curve_amp)
-            A = cg.assemble(box, kappas[l])
+            box = Box(Nc, degree, curve_amp, lo=lo, length=length)
+            A = cg.assemble(box, kappas[l], bc=bc)
             Dinv = 1.0 / A.diagonal()
             lev = {"box": box, "A": A, "Dinv": Dinv, "kappa": kappas[l]}
             if l == 0:
-                interior = ~box.boundary_mask()
+                interior = ~box.boundary_mask(bc)
                 Ai = A[interior][:, interior].toarray()
                 di = np.sqrt(Dinv[interior])
                 ev = np.linalg.eigvalsh(di[:, None] * Ai * di[None, :])
                 lev["lmin"], lev["lmax"] = float(ev.min()), float(ev.max())
                 lev["steps"] = coarse_steps(lev["lmin"], lev["lmax"], coarse_eps)
             else:
-                lam = lanczos_max_eig(A, Dinv, key=Nc, iters=eig_iters, bmask=box.boundary_mask())
+                lam = lanczos_max_eig(A, Dinv, key=Nc, iters=eig_iters, bmask=box.boundary_mask(bc))
                 lev["lambda"] = lam
                 lev["lo"], lev["hi"] = cheb_lo * lam, cheb_hi * lam
-                lev["P"] = prolongation(self.levels[l - 1]["box"], box)
+                lev["P"] = prolongation(self.levels[l - 1]["box"], box, bc)
             self.levels.append(lev)
         self.fine_products = 0
 
@@ -224,7 +226,8 @@ def pcg(A, b, precond, tol=1e-10, maxit=200):
 
 
 def solve(fine_cells, degree, b=None, kappa=None, curve_amp=0.0, tol=1e-10, maxit=200, **mg_kwargs):
-    """GMG-PCG solve of the Dirichlet problem; b defaults to the sine right-hand side."""
+    """GMG-PCG solve (boundary conditions and domain from mg_kwargs, default Dirichlet on
+    the unit cube); b defaults to the sine right-hand side."""
     mg = Multigrid(fine_cells, degree, kappa=kappa, curve_amp=curve_amp, **mg_kwargs)
     fine = mg.levels[-1]
     if b is None:

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmfl.so")
 MFL_OK, MFL_EINVAL, MFL_ENOCONV, MFL_EBREAKDOWN, MFL_EHIP, MFL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CG, SIPG = 0, 1
 CARTESIAN, CURVED = 0, 1
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 F64, F32 = 0, 1
 _DT = {F64: torch.float64, F32: torch.float32}
 
@@ -42,6 +42,8 @@ class Params(ctypes.Structure):
         ("coarse_tol", ctypes.c_double),
         ("mg_precision", ctypes.c_int),
         ("build_mg", ctypes.c_int),
+        ("domain_lo", ctypes.c_double),
+        ("domain_len", ctypes.c_double),
     ]
 
 
@@ -63,6 +65,7 @@ SIGNATURES = {
     "mfl_vcycle": (ctypes.c_int, [P, P, P, P]),
     "mfl_pcg_solve": (ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_int, IP, DP, P]),
     "mfl_rhs_sine": (ctypes.c_int, [P, P, P]),
+    "mfl_rhs_gaussians": (ctypes.c_int, [P, P, P]),
     "mfl_adjoint_solve": (ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_int, IP, DP, P]),
     "mfl_kappa_gradient": (ctypes.c_int, [P, P, P, P, P]),
     "mfl_profile": (ctypes.c_int, [P, ctypes.c_int, IP, DP]),
@@ -103,7 +106,8 @@ def _ptr(t):
 
 def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.1, bc=DIRICHLET,
                 penalty_factor=1.0, build_mg=False, mg_precision=F64, min_level_cells=2,
-                cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3):
+                cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3,
+                domain_lo=0.0, domain_len=1.0):
     p = Params()
     _check(lib().mfl_default_params(ctypes.byref(p)))
     p.degree, p.cells_per_dim, p.min_level_cells = degree, cells_per_dim, min_level_cells
@@ -111,6 +115,7 @@ def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.
     p.penalty_factor, p.build_mg, p.mg_precision = penalty_factor, int(bool(build_mg)), mg_precision
     p.cheb_degree, p.cheb_lo, p.cheb_hi = cheb_degree, cheb_lo, cheb_hi
     p.eig_iters, p.coarse_tol = eig_iters, coarse_tol
+    p.domain_lo, p.domain_len = domain_lo, domain_len
     return p
 
 
@@ -223,6 +228,12 @@ class Problem:
     def rhs_sine(self):
         b = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         _check(lib().mfl_rhs_sine(self.handle, _ptr(b), _stream()))
+        return b
+
+    def rhs_gaussians(self):
+        """Right-hand side of the three-Gaussian example (mfl_rhs_gaussians)."""
+        b = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        _check(lib().mfl_rhs_gaussians(self.handle, _ptr(b), _stream()))
         return b
 
     def _solve(self, fn, b, rtol, maxit, x, raise_on_noconv):

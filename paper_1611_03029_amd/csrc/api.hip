@@ -44,7 +44,10 @@ int check_params(const mfl_params *p) {
   if (p->disc != MFL_DISC_CG && p->disc != MFL_DISC_SIPG) return fail(MFL_EINVAL, "unknown disc %d", p->disc);
   if (p->geometry != MFL_GEOM_CARTESIAN && p->geometry != MFL_GEOM_CURVED)
     return fail(MFL_EINVAL, "unknown geometry %d", p->geometry);
-  if (p->bc != MFL_BC_DIRICHLET && p->bc != MFL_BC_NEUMANN) return fail(MFL_EINVAL, "unknown bc %d", p->bc);
+  if (p->bc != MFL_BC_DIRICHLET && p->bc != MFL_BC_NEUMANN && p->bc != MFL_BC_MIXED)
+    return fail(MFL_EINVAL, "unknown bc %d", p->bc);
+  if (!(std::isfinite(p->domain_lo) && p->domain_len > 0.0 && std::isfinite(p->domain_len)))
+    return fail(MFL_EINVAL, "need a finite domain_lo and 0 < domain_len < inf");
   if (p->mg_precision != MFL_F64 && p->mg_precision != MFL_F32)
     return fail(MFL_EINVAL, "unknown mg_precision %d", p->mg_precision);
   if (p->disc == MFL_DISC_SIPG) {
@@ -58,9 +61,11 @@ int check_params(const mfl_params *p) {
     // the map is checked cell by cell at setup only through the sign of det J at the
     // quadrature points, so keep the amplitude in the range where it cannot fold.
     if (!(std::fabs(p->curve_amp) <= 0.15)) return fail(MFL_EINVAL, "|curve_amp| must be <= 0.15");
+    if (p->domain_lo != 0.0 || p->domain_len != 1.0)
+      return fail(MFL_EINVAL, "the curved map is defined on the unit cube (domain_lo 0, domain_len 1)");
   }
   if (p->build_mg) {
-    if (p->bc != MFL_BC_DIRICHLET) return fail(MFL_EINVAL, "multigrid requires Dirichlet conditions");
+    if (p->bc == MFL_BC_NEUMANN) return fail(MFL_EINVAL, "multigrid requires Dirichlet conditions on some faces");
     if (p->min_level_cells < 1) return fail(MFL_EINVAL, "min_level_cells must be >= 1");
     int Nc = p->cells_per_dim;
     while (Nc > p->min_level_cells) {
@@ -128,12 +133,14 @@ int64_t layout(Context &c, char *base) {
       L.d = b.take<char>(L.ndofs * es);
     }
   }
-  if (p.build_mg) {
+  {
     const int64_t N = c.levels.back().ndofs;
     c.r = b.take<double>(N);
     c.z = b.take<double>(N);
-    c.pv = b.take<double>(N);
-    c.q = b.take<double>(N);
+    if (p.build_mg) {
+      c.pv = b.take<double>(N);
+      c.q = b.take<double>(N);
+    }
   }
   c.partials = b.take<double>(kReduceBlocks);
   c.scalars = b.take<double>(kNumScalars);
@@ -151,7 +158,7 @@ void init_context(Context &c, const mfl_params &p) {
     L.N1 = c.k * Nc + 1;
     L.ncells = int64_t(Nc) * Nc * Nc;
     L.ndofs = p.disc == MFL_DISC_CG ? int64_t(L.N1) * L.N1 * L.N1 : L.ncells * c.n * c.n * c.n;
-    L.h = 1.0 / Nc;
+    L.h = p.domain_len / Nc;
     c.levels.push_back(L);
   }
 }
@@ -234,7 +241,7 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
   Level &L = c.levels[l];
   const int64_t N = L.ndofs;
   double *r = c.r, *z = c.z, *p = c.pv, *q = c.q;
-  HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), s));
+  HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), dirichlet_mask(c.p), s));
   HIP_TRY(launch_jacobi(L.dinv64, r, z, N, s));
   HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
@@ -287,7 +294,9 @@ int rebuild_kappa_dependent(Context &c, hipStream_t s) {
     double lmin, lmax;
     int rc;
     if (l == 0) {
-      const int interior = (L.N1 - 2) * (L.N1 - 2) * (L.N1 - 2);
+      // unknowns without Dirichlet conditions: N1 - (number of Dirichlet faces) per direction
+      const int dm = dirichlet_mask(c.p), m1 = L.N1 - (dm & 1) - ((dm >> 1) & 1);
+      const int interior = m1 * m1 * m1;
       if ((rc = lanczos(c, l, interior + 50, true, a, b, s))) return rc;
       tridiag_extremes(a, b, lmin, lmax);
       L.coarse_lmin = lmin;
@@ -433,6 +442,8 @@ int mfl_default_params(mfl_params *p) {
   p->coarse_tol = 1e-3;
   p->mg_precision = MFL_F64;
   p->build_mg = 0;
+  p->domain_lo = 0.0;
+  p->domain_len = 1.0;
   return MFL_OK;
 }
 
@@ -619,6 +630,24 @@ int mfl_rhs_sine(mfl_handle h, double *b, void *stream) {
   return MFL_OK;
 }
 
+int mfl_rhs_gaussians(mfl_handle h, double *b, void *stream) {
+  if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "the three-Gaussian right-hand side is CG only");
+  if (h->p.geometry != MFL_GEOM_CARTESIAN)
+    return fail(MFL_EUNSUPPORTED, "the three-Gaussian right-hand side needs a Cartesian mesh");
+  if (!b) return fail(MFL_EINVAL, "b is NULL");
+  hipStream_t s = as_stream(stream);
+  const Level &F = h->levels.back();
+  // forcing and Neumann loads into b; x0 = Dirichlet data in r; z = A0 x0 (operator
+  // without boundary conditions); then b = x0 on Dirichlet DoFs and b - z elsewhere
+  HIP_TRY(launch_rhs_gaussians(*h, F, b, s));
+  HIP_TRY(launch_gaussian_dirichlet(*h, F, h->r, s));
+  HIP_TRY(launch_cg_apply(*h, F, MFL_F64, h->r, h->z, s, 0));
+  HIP_TRY(launch_cg_halo_add(*h, F, MFL_F64, h->z, s, 0));
+  HIP_TRY(launch_lift(*h, F, b, h->r, h->z, s));
+  return MFL_OK;
+}
+
 int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double rtol, int maxit,
                       int *iters, double *final_rel_res, void *stream) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
@@ -630,7 +659,7 @@ int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double r
   // the right-hand side with zeroed Dirichlet entries is staged in the solution vector
   if (dJdu != lambda)
     HIP_TRY(hipMemcpyAsync(lambda, dJdu, F.ndofs * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(launch_zero_boundary(lambda, F, s));
+  HIP_TRY(launch_zero_boundary(lambda, F, dirichlet_mask(h->p), s));
   HIP_TRY(hipMemcpyAsync(h->q, lambda, F.ndofs * sizeof(double), hipMemcpyDeviceToDevice, s));
   // pcg() uses r, z, pv, q as work: move the staged right-hand side to the level's x-free slot
   double *rhs = h->q;

@@ -28,6 +28,16 @@ __device__ __forceinline__ void lds_add(T *p, T v) {
 
 __device__ __forceinline__ bool on_boundary(int g, int N1) { return g == 0 || g == N1 - 1; }
 
+// Grid index g (0..N1-1) along one direction lies on a face with Dirichlet conditions:
+// dmask bit 0 marks the lower faces (g = 0), bit 1 the upper faces (g = N1 - 1).
+__device__ __forceinline__ bool on_dirichlet(int g, int N1, int dmask) {
+  return ((dmask & 1) && g == 0) || ((dmask & 2) && g == N1 - 1);
+}
+
+__device__ __forceinline__ bool dirichlet_dof(int x, int y, int z, int N1, int dmask) {
+  return on_dirichlet(x, N1, dmask) || on_dirichlet(y, N1, dmask) || on_dirichlet(z, N1, dmask);
+}
+
 // Synchronization point among the lanes of one wavefront for data exchanged through LDS.
 // A wavefront's LDS instructions execute in issue order, so only the compiler has to be
 // kept from moving LDS accesses across this point; no instruction is emitted.
@@ -65,6 +75,7 @@ Tab<N, T> shrink_tab(const Tab<kMaxN, T> &t) {
   for (int i = 0; i < N; ++i) {
     o.w[i] = t.w[i];
     o.gll[i] = t.gll[i];
+    o.xg[i] = t.xg[i];
   }
   return o;
 }

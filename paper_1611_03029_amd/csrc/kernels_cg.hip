@@ -78,11 +78,11 @@ struct CellCtx {
   bool bxy;          // lane's z-line lies on a Dirichlet x- or y-face
   int64_t base;      // grid index of the lane's z-line start
   int64_t plane;     // N1^2
-  int N1, K, dirichlet;
+  int N1, K, dmask;
 };
 
 __device__ __forceinline__ CellCtx make_ctx(int K, int n, int p, bool inblk, bool active, int cx, int cy,
-                                            int cz, int N1, int dirichlet) {
+                                            int cz, int N1, int dmask) {
   CellCtx c;
   c.i0 = p % n;
   c.i1 = p / n;
@@ -90,17 +90,17 @@ __device__ __forceinline__ CellCtx make_ctx(int K, int n, int p, bool inblk, boo
   c.inblk = inblk;
   c.active = active;
   const int gx = cx * K + c.i0, gy = cy * K + c.i1;
-  c.bxy = dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1));
+  c.bxy = on_dirichlet(gx, N1, dmask) || on_dirichlet(gy, N1, dmask);
   c.plane = int64_t(N1) * N1;
   c.base = gx + int64_t(N1) * gy + c.plane * (int64_t(cz) * K);
   c.N1 = N1;
   c.K = K;
-  c.dirichlet = dirichlet;
+  c.dmask = dmask;
   return c;
 }
 
 __device__ __forceinline__ bool z_bnd(const CellCtx &c, int l) {
-  return c.bxy || (c.dirichlet && on_boundary(c.cz * c.K + l, c.N1));
+  return c.bxy || on_dirichlet(c.cz * c.K + l, c.N1, c.dmask);
 }
 
 // The lane's z-line of src (Dirichlet DoFs and inactive lanes read as zero: the columns of
@@ -337,7 +337,7 @@ struct BrickGrid {
   int Nc, N1;
   int sx;              // cells per brick in x (multiple of the chunk width)
   int nbx, nby, nbz;   // bricks per direction
-  int dirichlet;
+  int dmask;           // Dirichlet face mask
 };
 
 // Halo record of a brick (upper faces owned by neighbouring bricks), M = brick extent in
@@ -394,7 +394,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
     const int cx = cx0 + j * CX + lx;
     const bool active = inblk && j < nchunks && cx < Nc && cy < Nc && cz < Nc;
     cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
-    cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, bg.dirichlet);
+    cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, bg.dmask);
   };
 
 #pragma unroll
@@ -451,7 +451,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   const int64_t gbase = gx0 + int64_t(N1) * gy0 + plane * gz0;
   // interior bricks without Dirichlet DoFs and without cut-off cells need no per-item tests
   const bool plain = gx0 + MX < N1 - 1 && gy0 + MY < N1 - 1 && gz0 + MZ < N1 - 1 &&
-                     !(bg.dirichlet && (gx0 == 0 || gy0 == 0 || gz0 == 0));
+                     !((bg.dmask & 1) && (gx0 == 0 || gy0 == 0 || gz0 == 0));
   constexpr int OWN = MX * MY * MZ, ITO = (OWN + kBlock - 1) / kBlock;
 #pragma unroll
   for (int it = 0; it < ITO; ++it) {
@@ -465,8 +465,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
       } else {
         const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
         if (gx < N1 && gy < N1 && gz < N1) {
-          const bool bnd =
-              bg.dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1));
+          const bool bnd = dirichlet_dof(gx, gy, gz, N1, bg.dmask);
           dst[gi] = bnd ? src[gi] : v;
         }
       }
@@ -503,8 +502,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
           hrec[i] = v;
         } else {
           const int64_t gi = gbase + (X + N1 * Y) + plane * Z;
-          const bool bnd =
-              bg.dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1));
+          const bool bnd = dirichlet_dof(gx, gy, gz, N1, bg.dmask);
           dst[gi] = bnd ? src[gi] : v;
         }
       }
@@ -548,7 +546,7 @@ halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
       if (g[0] % MX == 0 && g[0] / MX >= 1 && g[0] / MX < bg.nbx) continue;
       if (g[1] % MY == 0 && g[1] / MY >= 1 && g[1] / MY < bg.nby) continue;
     }
-    if (bg.dirichlet && (on_boundary(g[0], N1) || on_boundary(g[1], N1) || on_boundary(g[2], N1)))
+    if (dirichlet_dof(g[0], g[1], g[2], N1, bg.dmask))
       continue;
     const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
     int b[3], X[3];
@@ -575,7 +573,7 @@ halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
 template <int K, typename T, bool CURVED>
 __global__ void __launch_bounds__(kBlock)
 kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restrict__ grad,
-                  const T *__restrict__ metric, int Nc, int N1, T h, int dirichlet) {
+                  const T *__restrict__ metric, int Nc, int N1, T h, int dmask) {
   constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
   using S = Shape<K>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, CPB = S::cpb;
@@ -593,7 +591,7 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
     cy = int((cell / Nc) % Nc);
     cz = int(cell / (int64_t(Nc) * Nc));
   }
-  const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, dirichlet);
+  const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, dmask);
   const int slot = inblk ? lc : 0;
   T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[2] + slot * n3;
   T ul[n];
@@ -624,12 +622,12 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
 // dst = src on Dirichlet DoFs, 0 elsewhere.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-boundary_init_kernel(const T *__restrict__ src, T *__restrict__ dst, int N1, int dirichlet) {
+boundary_init_kernel(const T *__restrict__ src, T *__restrict__ dst, int N1, int dmask) {
   const int64_t n = int64_t(N1) * N1 * N1;
   for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * kBlock) {
     const int x = int(i % N1), y = int((i / N1) % N1), z = int(i / (int64_t(N1) * N1));
-    const bool bnd = dirichlet && (on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(z, N1));
+    const bool bnd = dirichlet_dof(x, y, z, N1, dmask);
     dst[i] = bnd ? src[i] : T(0);
   }
 }
@@ -643,7 +641,7 @@ inline int grid_for(int64_t items, int cap = 65536) {
 // that there are about MFL_TARGET_BRICKS bricks (enough work-groups to fill the chip) when
 // the mesh allows, which keeps the strided x-face halos to a few planes.
 template <int K>
-BrickGrid brick_grid(int Nc, int N1, int dirichlet) {
+BrickGrid brick_grid(int Nc, int N1, int dmask) {
   BrickGrid bg;
   bg.Nc = Nc;
   bg.N1 = N1;
@@ -651,7 +649,7 @@ BrickGrid brick_grid(int Nc, int N1, int dirichlet) {
   bg.nbx = (Nc + bg.sx - 1) / bg.sx;
   bg.nby = (Nc + Brick<K>::y - 1) / Brick<K>::y;
   bg.nbz = (Nc + Brick<K>::z - 1) / Brick<K>::z;
-  bg.dirichlet = dirichlet;
+  bg.dmask = dmask;
   return bg;
 }
 
@@ -661,7 +659,7 @@ int64_t cg_halo_elements(int k, int Nc) {
   BrickGrid bg{};
   int my = 0, mz = 0;
 #define CASE(K)                              \
-  bg = brick_grid<K>(Nc, K * Nc + 1, 1);     \
+  bg = brick_grid<K>(Nc, K * Nc + 1, 3);     \
   my = Brick<K>::y * K;                      \
   mz = Brick<K>::z * K;                      \
   break
@@ -682,7 +680,7 @@ int64_t cg_halo_elements(int k, int Nc) {
 
 hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
                                 void *dst, hipStream_t s) {
-  const int dir = c.p.bc == MFL_BC_DIRICHLET;
+  const int dir = dirichlet_mask(c.p);
   const int grid = grid_for(L.ndofs, 8192);
   if (dtype == MFL_F64)
     boundary_init_kernel<double><<<grid, kBlock, 0, s>>>((const double *)src, (double *)dst, L.N1, dir);
@@ -693,8 +691,8 @@ hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, con
 
 template <int K, typename T>
 static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, T> &tab, const T *kappa,
-                             const T *metric, const T *src, T *dst, T *halo, hipStream_t s) {
-  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, c.p.bc == MFL_BC_DIRICHLET);
+                             const T *metric, const T *src, T *dst, T *halo, hipStream_t s, int dmask) {
+  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, dmask < 0 ? dirichlet_mask(c.p) : dmask);
   const int nb = bg.nbx * bg.nby * bg.nbz;
   (void)tab;
   if (c.p.geometry == MFL_GEOM_CURVED)
@@ -705,8 +703,9 @@ static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, 
 }
 
 template <int K, typename T>
-static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *halo, hipStream_t s) {
-  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, c.p.bc == MFL_BC_DIRICHLET);
+static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *halo, hipStream_t s,
+                            int dmask) {
+  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, dmask < 0 ? dirichlet_mask(c.p) : dmask);
   const int64_t total = int64_t(bg.nbx - 1 + bg.nby - 1 + bg.nbz - 1) * L.N1 * L.N1;
   if (total == 0) return hipSuccess;
   if (total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit face index space
@@ -715,26 +714,27 @@ static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *h
 }
 
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
-                           hipStream_t s) {
+                           hipStream_t s, int dmask) {
   if (dtype == MFL_F64) {
-#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s)
+#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s, dmask)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   } else {
-#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s)
+#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s, dmask)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s) {
+hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s,
+                              int dmask) {
   if (dtype == MFL_F64) {
-#define CASE(K) return cg_halo_k<K, double>(c, L, (double *)dst, (const double *)L.halo, s)
+#define CASE(K) return cg_halo_k<K, double>(c, L, (double *)dst, (const double *)L.halo, s, dmask)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   } else {
-#define CASE(K) return cg_halo_k<K, float>(c, L, (float *)dst, (const float *)L.halo, s)
+#define CASE(K) return cg_halo_k<K, float>(c, L, (float *)dst, (const float *)L.halo, s, dmask)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }
@@ -746,7 +746,7 @@ static hipError_t kappa_grad_k(const Context &c, const Level &L, const double *u
                                double *grad, hipStream_t s) {
   constexpr int CPB = Shape<K>::cpb;
   const int grid = int((L.ncells + CPB - 1) / CPB);
-  const int dir = c.p.bc == MFL_BC_DIRICHLET;
+  const int dir = dirichlet_mask(c.p);
   if (c.p.geometry == MFL_GEOM_CURVED)
     kappa_grad_kernel<K, double, true><<<grid, kBlock, 0, s>>>(u, lam, grad, L.metric64, L.Nc, L.N1, L.h, dir);
   else

@@ -49,12 +49,12 @@ coarsen_kappa_kernel(const double *__restrict__ fine, double *__restrict__ c64, 
 // Dirichlet DoFs get diagonal 1 (identity rows); inverse and FP32 copies.
 __global__ void __launch_bounds__(kBlock)
 diag_finalize_kernel(double *__restrict__ d64, double *__restrict__ i64, float *__restrict__ d32,
-                     float *__restrict__ i32, int N1, int dirichlet) {
+                     float *__restrict__ i32, int N1, int dmask) {
   const int64_t n = int64_t(N1) * N1 * N1;
   GRID_STRIDE(i, n) {
     const int x = int(i % N1), y = int((i / N1) % N1), z = int(i / (int64_t(N1) * N1));
     double v = d64[i];
-    if (dirichlet && (on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(z, N1))) v = 1.0;
+    if (dirichlet_dof(x, y, z, N1, dmask)) v = 1.0;
     d64[i] = v;
     i64[i] = 1.0 / v;
     d32[i] = float(v);
@@ -99,7 +99,7 @@ cheb_step_kernel(const T *__restrict__ b, const T *__restrict__ ax, const T *__r
 // written by exactly one coarse cell (half-open ownership), so no atomics are needed.
 template <int K, typename TC, typename TF>
 __global__ void __launch_bounds__(kBlock)
-prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, TransferTab tt) {
+prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int dmask, TransferTab tt) {
   constexpr int n = K + 1, m = 2 * K + 1;
   constexpr int s0 = (n * n * n > m * m * n) ? n * n * n : m * m * n;
   __shared__ double P[m * n];
@@ -111,7 +111,7 @@ prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, Trans
   for (int i = threadIdx.x; i < n * n * n; i += kBlock) {
     const int a = i % n, b = (i / n) % n, l = i / (n * n);
     const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
-    const bool bnd = on_boundary(gx, N1c) || on_boundary(gy, N1c) || on_boundary(gz, N1c);
+    const bool bnd = dirichlet_dof(gx, gy, gz, N1c, dmask);
     b0[i] = bnd ? TF(0) : TF(xc[gx + int64_t(N1c) * (gy + int64_t(N1c) * gz)]);
   }
   __syncthreads();
@@ -134,7 +134,7 @@ prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, Trans
     if ((I == m - 1 && cx < Ncc - 1) || (J == m - 1 && cy < Ncc - 1) || (L == m - 1 && cz < Ncc - 1))
       continue;                                             // owned by the next coarse cell
     const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
-    if (on_boundary(fx, N1f) || on_boundary(fy, N1f) || on_boundary(fz, N1f)) continue;
+    if (dirichlet_dof(fx, fy, fz, N1f, dmask)) continue;
     TF s = 0;
     for (int a = 0; a < n; ++a) s += TF(P[I * n + a]) * b0[L * m * n + J * n + a];
     xf[fx + int64_t(N1f) * (fy + int64_t(N1f) * fz)] += s;
@@ -147,7 +147,7 @@ prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, Trans
 template <int K, typename TF, typename TC>
 __global__ void __launch_bounds__(kBlock)
 restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__restrict__ bc, int Ncc,
-                TransferTab tt) {
+                int dmask, TransferTab tt) {
   constexpr int n = K + 1, m = 2 * K + 1;
   __shared__ double P[m * n];
   __shared__ TF r[m * m * m], t1[m * m * n];
@@ -159,7 +159,7 @@ restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__res
     const int I = i % m, J = (i / m) % m, L = i / (m * m);
     const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
     TF v = 0;
-    if (!(on_boundary(fx, N1f) || on_boundary(fy, N1f) || on_boundary(fz, N1f))) {
+    if (!dirichlet_dof(fx, fy, fz, N1f, dmask)) {
       const int64_t g = fx + int64_t(N1f) * (fy + int64_t(N1f) * fz);
       TF wgt = 1;
       if ((I == 0 && cx > 0) || (I == m - 1 && cx < Ncc - 1)) wgt *= TF(0.5);
@@ -187,7 +187,7 @@ restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__res
   for (int i = threadIdx.x; i < n * n * n; i += kBlock) {   // z: coarse DoF (a, b, l)
     const int a = i % n, b = (i / n) % n, l = i / (n * n);
     const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
-    if (on_boundary(gx, N1c) || on_boundary(gy, N1c) || on_boundary(gz, N1c)) continue;
+    if (dirichlet_dof(gx, gy, gz, N1c, dmask)) continue;
     TF s = 0;
     for (int L = 0; L < m; ++L) s += TF(P[L * n + l]) * r[L * n * n + b * n + a];
     atomic_add(bc + gx + int64_t(N1c) * (gy + int64_t(N1c) * gz), TC(s));
@@ -252,7 +252,7 @@ pcg_update_p_kernel(double *__restrict__ p, const double *__restrict__ z, const 
 // SplitMix64 counter stream (Steele, Lea, Flood 2014): value i of stream `key` is the
 // finalizer applied to key + (i+1) * 0x9E3779B97F4A7C15, mapped to [-1, 1).
 __global__ void __launch_bounds__(kBlock)
-random_start_kernel(double *__restrict__ v, int N1, uint64_t key) {
+random_start_kernel(double *__restrict__ v, int N1, uint64_t key, int dmask) {
   const int64_t n = int64_t(N1) * N1 * N1;
   GRID_STRIDE(i, n) {
     uint64_t z = key + uint64_t(i + 1) * 0x9E3779B97F4A7C15ull;
@@ -261,7 +261,7 @@ random_start_kernel(double *__restrict__ v, int N1, uint64_t key) {
     z = z ^ (z >> 31);
     const double u = 2.0 * double(z >> 11) * 0x1.0p-53 - 1.0;
     const int x = int(i % N1), y = int((i / N1) % N1), zz = int(i / (int64_t(N1) * N1));
-    const bool bnd = on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(zz, N1);
+    const bool bnd = dirichlet_dof(x, y, zz, N1, dmask);
     v[i] = bnd ? 0.0 : u;
   }
 }
@@ -272,11 +272,11 @@ jacobi_kernel(const double *__restrict__ dinv, const double *__restrict__ r, dou
   GRID_STRIDE(i, n) z[i] = dinv[i] * r[i];
 }
 
-__global__ void __launch_bounds__(kBlock) zero_boundary_kernel(double *__restrict__ v, int N1) {
+__global__ void __launch_bounds__(kBlock) zero_boundary_kernel(double *__restrict__ v, int N1, int dmask) {
   const int64_t n = int64_t(N1) * N1 * N1;
   GRID_STRIDE(i, n) {
     const int x = int(i % N1), y = int((i / N1) % N1), z = int(i / (int64_t(N1) * N1));
-    if (on_boundary(x, N1) || on_boundary(y, N1) || on_boundary(z, N1)) v[i] = 0.0;
+    if (dirichlet_dof(x, y, z, N1, dmask)) v[i] = 0.0;
   }
 }
 
@@ -311,7 +311,7 @@ hipError_t launch_coarsen_kappa(const Level &coarse, const Level &fine, hipStrea
 
 hipError_t launch_diag_finalize(const Context &c, const Level &L, hipStream_t s) {
   diag_finalize_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(L.diag64, L.dinv64, L.diag32, L.dinv32,
-                                                            L.N1, c.p.bc == MFL_BC_DIRICHLET);
+                                                            L.N1, dirichlet_mask(c.p));
   return hipGetLastError();
 }
 
@@ -355,11 +355,11 @@ static hipError_t prolongate_k(const Context &c, const Level &coarse, const void
                                void *xf, int fd, hipStream_t s) {
   const int grid = int(coarse.ncells);
   if (cd == MFL_F64 && fd == MFL_F64)
-    prolongate_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)xc, (double *)xf, coarse.Nc, c.transfer);
+    prolongate_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)xc, (double *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
   else if (cd == MFL_F64 && fd == MFL_F32)
-    prolongate_kernel<K, double, float><<<grid, kBlock, 0, s>>>((const double *)xc, (float *)xf, coarse.Nc, c.transfer);
+    prolongate_kernel<K, double, float><<<grid, kBlock, 0, s>>>((const double *)xc, (float *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
   else if (cd == MFL_F32 && fd == MFL_F32)
-    prolongate_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)xc, (float *)xf, coarse.Nc, c.transfer);
+    prolongate_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)xc, (float *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -379,11 +379,11 @@ static hipError_t restrict_k(const Context &c, const Level &coarse, const void *
                              int fd, void *bc, int cd, hipStream_t s) {
   const int grid = int(coarse.ncells);
   if (fd == MFL_F64 && cd == MFL_F64)
-    restrict_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)bf, (const double *)axf, (double *)bc, coarse.Nc, c.transfer);
+    restrict_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)bf, (const double *)axf, (double *)bc, coarse.Nc, dirichlet_mask(c.p), c.transfer);
   else if (fd == MFL_F32 && cd == MFL_F64)
-    restrict_kernel<K, float, double><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (double *)bc, coarse.Nc, c.transfer);
+    restrict_kernel<K, float, double><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (double *)bc, coarse.Nc, dirichlet_mask(c.p), c.transfer);
   else if (fd == MFL_F32 && cd == MFL_F32)
-    restrict_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (float *)bc, coarse.Nc, c.transfer);
+    restrict_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (float *)bc, coarse.Nc, dirichlet_mask(c.p), c.transfer);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -424,8 +424,8 @@ hipError_t launch_pcg_update_p(double *p, const double *z, const double *scalars
   return hipGetLastError();
 }
 
-hipError_t launch_random_start(double *v, const Level &L, uint64_t key, hipStream_t s) {
-  random_start_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1, key);
+hipError_t launch_random_start(double *v, const Level &L, uint64_t key, int dmask, hipStream_t s) {
+  random_start_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1, key, dmask);
   return hipGetLastError();
 }
 
@@ -434,8 +434,8 @@ hipError_t launch_jacobi(const double *dinv, const double *r, double *z, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_zero_boundary(double *v, const Level &L, hipStream_t s) {
-  zero_boundary_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1);
+hipError_t launch_zero_boundary(double *v, const Level &L, int dmask, hipStream_t s) {
+  zero_boundary_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1, dmask);
   return hipGetLastError();
 }
 

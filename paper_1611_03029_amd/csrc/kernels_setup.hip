@@ -1,5 +1,6 @@
 // Setup kernels of the continuous Q_k operator (FP64): per-quadrature-point metric of
-// curved cells, the matrix diagonal for the Jacobi smoother, and the sine right-hand side.
+// curved cells, the matrix diagonal for the Jacobi smoother, and the right-hand sides of
+// the sine problem and of the three-Gaussian example (Sec. 5, eq. pois_analytic).
 #include <cmath>
 
 #include "device_common.h"
@@ -83,7 +84,7 @@ metric_kernel(double *__restrict__ m64, float *__restrict__ m32, int Nc, double 
 template <int K>
 __global__ void __launch_bounds__(kBlock)
 diag_cart_kernel(double *__restrict__ diag, const double *__restrict__ kappa, int Nc, int N1,
-                 double h, int dirichlet, Tab<K + 1, double> tb) {
+                 double h, int dmask, Tab<K + 1, double> tb) {
   constexpr int n = K + 1, n3 = n * n * n;
   __shared__ double Md[n], Kd[n];
   if (threadIdx.x < n) {
@@ -99,7 +100,7 @@ diag_cart_kernel(double *__restrict__ diag, const double *__restrict__ kappa, in
     const int i = int(id - cell * n3), a = i % n, b = (i / n) % n, l = i / (n * n);
     const int gx = int(cell % Nc) * K + a, gy = int((cell / Nc) % Nc) * K + b,
               gz = int(cell / (int64_t(Nc) * Nc)) * K + l;
-    if (dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1))) continue;
+    if (dirichlet_dof(gx, gy, gz, N1, dmask)) continue;
     const double v = kappa[cell] * h *
                      (Kd[a] * Md[b] * Md[l] + Md[a] * Kd[b] * Md[l] + Md[a] * Md[b] * Kd[l]);
     atomic_add(diag + gx + N1 * int64_t(gy) + plane * gz, v);
@@ -110,7 +111,7 @@ diag_cart_kernel(double *__restrict__ diag, const double *__restrict__ kappa, in
 template <int K>
 __global__ void __launch_bounds__(kBlock)
 diag_curved_kernel(double *__restrict__ diag, const double *__restrict__ kappa,
-                   const double *__restrict__ metric, int Nc, int N1, int dirichlet,
+                   const double *__restrict__ metric, int Nc, int N1, int dmask,
                    Tab<K + 1, double> tb) {
   constexpr int n = K + 1, n3 = n * n * n;
   __shared__ double S[n * n], Sd[n * n];
@@ -127,7 +128,7 @@ diag_curved_kernel(double *__restrict__ diag, const double *__restrict__ kappa,
     const int i = int(id - cell * n3), a = i % n, b = (i / n) % n, l = i / (n * n);
     const int gx = int(cell % Nc) * K + a, gy = int((cell / Nc) % Nc) * K + b,
               gz = int(cell / (int64_t(Nc) * Nc)) * K + l;
-    if (dirichlet && (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1))) continue;
+    if (dirichlet_dof(gx, gy, gz, N1, dmask)) continue;
     const double *G = metric + cell * (6 * n3);
     double acc = 0;
     for (int q = 0; q < n3; ++q) {
@@ -142,11 +143,56 @@ diag_curved_kernel(double *__restrict__ diag, const double *__restrict__ kappa,
   }
 }
 
-// Right-hand side b_i = sum_q w_q det J_q f(x_q) phi_i(xi_q), f = 3 pi^2 sin sin sin, with
-// x_q the isoparametric image of the Gauss point.  One work-group per cell.
-template <int K>
+// f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z): the forcing of u = sin sin sin.
+struct SineForcing {
+  __device__ double operator()(const double x[3]) const {
+    return 3.0 * M_PI * M_PI * sin(M_PI * x[0]) * sin(M_PI * x[1]) * sin(M_PI * x[2]);
+  }
+};
+
+// The solution of the smooth-solution example (Sec. 5, eq. pois_analytic): three Gaussians
+// of width alpha = 1/5, u = (alpha sqrt(2 pi))^-3 sum_j exp(-|x - x_j|^2 / alpha^2).
+// Returns u, grad u and Laplace u (in 3D, Laplace exp(-r^2/a^2) = (4 r^2/a^4 - 6/a^2) exp).
+__device__ inline void gaussians(const double x[3], double &u, double g[3], double &lap) {
+  const double alpha = 0.2, ia2 = 1.0 / (alpha * alpha);
+  const double centres[3][3] = {{-0.5, 0.5, 0.25}, {-0.6, -0.5, -0.125}, {0.5, -0.5, 0.5}};
+  const double s = 1.0 / (alpha * sqrt(2.0 * M_PI)), scale = s * s * s;
+  u = 0.0;
+  lap = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    const double d0 = x[0] - centres[j][0], d1 = x[1] - centres[j][1], d2 = x[2] - centres[j][2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double e = exp(-r2 * ia2);
+    u += e;
+    g[0] -= 2.0 * ia2 * d0 * e;
+    g[1] -= 2.0 * ia2 * d1 * e;
+    g[2] -= 2.0 * ia2 * d2 * e;
+    lap += (4.0 * r2 * ia2 * ia2 - 6.0 * ia2) * e;
+  }
+  u *= scale;
+  lap *= scale;
+  g[0] *= scale;
+  g[1] *= scale;
+  g[2] *= scale;
+}
+
+// f = -Laplace(u) of the three-Gaussian solution.
+struct GaussianForcing {
+  __device__ double operator()(const double x[3]) const {
+    double u, g[3], lap;
+    gaussians(x, u, g, lap);
+    return -lap;
+  }
+};
+
+// Right-hand side b_i = sum_q w_q det J_q f(x_q) phi_i(xi_q), with x_q the isoparametric
+// image of the Gauss point (cells of [lo, lo + Nc h]^3).  DoFs on Dirichlet faces are
+// skipped.  One work-group per cell.
+template <int K, class F>
 __global__ void __launch_bounds__(kBlock)
-rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double amp, Tab<K + 1, double> tb) {
+rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double lo, double amp, int dmask,
+           Tab<K + 1, double> tb) {
   constexpr int n = K + 1, n3 = n * n * n;
   __shared__ double S[n * n], Sd[n * n], gll[n], w[n], fw[n3];
   for (int i = threadIdx.x; i < n * n; i += kBlock) {
@@ -165,7 +211,7 @@ rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double amp, Tab<K +
     double X[3][n], s1[3][n];
     for (int d = 0; d < 3; ++d)
       for (int i = 0; i < n; ++i) {
-        X[d][i] = (c[d] + gll[i]) * h;
+        X[d][i] = lo + (c[d] + gll[i]) * h;
         s1[d][i] = sin(M_PI * X[d][i]);
       }
     double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, xq[3] = {0, 0, 0};
@@ -186,21 +232,98 @@ rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double amp, Tab<K +
     const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                        J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    const double f = 3.0 * M_PI * M_PI * sin(M_PI * xq[0]) * sin(M_PI * xq[1]) * sin(M_PI * xq[2]);
-    fw[q] = w[q0] * w[q1] * w[q2] * det * f;
+    fw[q] = w[q0] * w[q1] * w[q2] * det * F()(xq);
   }
   __syncthreads();
   const int64_t plane = int64_t(N1) * N1;
   for (int i = threadIdx.x; i < n3; i += kBlock) {
     const int a = i % n, bb = (i / n) % n, l = i / (n * n);
     const int gx = c[0] * K + a, gy = c[1] * K + bb, gz = c[2] * K + l;
-    if (on_boundary(gx, N1) || on_boundary(gy, N1) || on_boundary(gz, N1)) continue;
+    if (dirichlet_dof(gx, gy, gz, N1, dmask)) continue;
     double s = 0;
     for (int q = 0; q < n3; ++q) {
       const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
       s += S[q0 * n + a] * S[q1 * n + bb] * S[q2 * n + l] * fw[q];
     }
     atomic_add(b + gx + N1 * int64_t(gy) + plane * gz, s);
+  }
+}
+
+// Neumann loads int_F g_N phi_i, g_N = grad u . n of the three-Gaussian solution (n the
+// outward normal), on the boundary faces without Dirichlet conditions of a Cartesian mesh
+// of [lo, lo + Nc h]^3.  One work-group per (domain face, cell face on it); k+1 Gauss
+// points per tangential direction; the face basis functions are products of the
+// tangential GLL bases.  Block b: face f = b / Nc^2 (direction f % 3, side f / 3).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+neumann_face_kernel(double *__restrict__ b, int Nc, int N1, double h, double lo, int dmask,
+                    Tab<K + 1, double> tb) {
+  constexpr int n = K + 1;
+  __shared__ double gw[n * n];
+  const int64_t per_face = int64_t(Nc) * Nc;
+  const int face = int(blockIdx.x / per_face);
+  const int e = face % 3, side = face / 3;
+  if ((dmask >> side) & 1) return;   // Dirichlet face: no load (uniform per work-group)
+  const int64_t r = blockIdx.x - face * per_face;
+  const int ta = e == 0 ? 1 : 0, tb2 = e == 2 ? 1 : 2;   // tangential directions
+  int c[3];
+  c[e] = side ? Nc - 1 : 0;
+  c[ta] = int(r % Nc);
+  c[tb2] = int(r / Nc);
+  for (int q = threadIdx.x; q < n * n; q += kBlock) {
+    const int q1 = q % n, q2 = q / n;
+    double x[3], u, g[3], lap;
+    x[e] = lo + (c[e] + side) * h;
+    x[ta] = lo + (c[ta] + tb.xg[q1]) * h;
+    x[tb2] = lo + (c[tb2] + tb.xg[q2]) * h;
+    gaussians(x, u, g, lap);
+    gw[q] = tb.w[q1] * tb.w[q2] * h * h * (side ? g[e] : -g[e]);
+  }
+  __syncthreads();
+  const int64_t plane = int64_t(N1) * N1;
+  for (int i = threadIdx.x; i < n * n; i += kBlock) {
+    const int i1 = i % n, i2 = i / n;
+    int gi[3];
+    gi[e] = c[e] * K + (side ? K : 0);
+    gi[ta] = c[ta] * K + i1;
+    gi[tb2] = c[tb2] * K + i2;
+    if (dirichlet_dof(gi[0], gi[1], gi[2], N1, dmask)) continue;
+    double s = 0;
+    for (int q = 0; q < n * n; ++q) s += tb.S[(q % n) * n + i1] * tb.S[(q / n) * n + i2] * gw[q];
+    atomic_add(b + gi[0] + N1 * int64_t(gi[1]) + plane * gi[2], s);
+  }
+}
+
+// x0 = u (three-Gaussian solution) interpolated at the Dirichlet DoFs of a Cartesian mesh,
+// 0 elsewhere.  Grid line g lies at lo + (c + gll[g - c K]) h, c = min(g / K, Nc - 1).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+gaussian_dirichlet_kernel(double *__restrict__ x0, int Nc, int N1, double h, double lo, int dmask,
+                          Tab<K + 1, double> tb) {
+  const int64_t nd = int64_t(N1) * N1 * N1;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < nd; i += int64_t(gridDim.x) * kBlock) {
+    const int g[3] = {int(i % N1), int((i / N1) % N1), int(i / (int64_t(N1) * N1))};
+    double v = 0.0;
+    if (dirichlet_dof(g[0], g[1], g[2], N1, dmask)) {
+      double x[3], gr[3], lap;
+      for (int d = 0; d < 3; ++d) {
+        const int c = min(g[d] / K, Nc - 1);
+        x[d] = lo + (c + tb.gll[g[d] - c * K]) * h;
+      }
+      gaussians(x, v, gr, lap);
+    }
+    x0[i] = v;
+  }
+}
+
+// b = x0 on Dirichlet DoFs, b - a0 elsewhere (a0 = A0 x0, the lifting of the Dirichlet data).
+__global__ void __launch_bounds__(kBlock)
+lift_kernel(double *__restrict__ b, const double *__restrict__ x0, const double *__restrict__ a0, int N1,
+            int dmask) {
+  const int64_t nd = int64_t(N1) * N1 * N1;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < nd; i += int64_t(gridDim.x) * kBlock) {
+    const int x = int(i % N1), y = int((i / N1) % N1), z = int(i / (int64_t(N1) * N1));
+    b[i] = dirichlet_dof(x, y, z, N1, dmask) ? x0[i] : b[i] - a0[i];
   }
 }
 
@@ -224,7 +347,7 @@ hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s) 
 
 hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s) {
   const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
-  const int dir = c.p.bc == MFL_BC_DIRICHLET;
+  const int dir = dirichlet_mask(c.p);
   hipError_t e = launch_fill(L.diag64, MFL_F64, L.ndofs, 0.0, s);
   if (e != hipSuccess) return e;
   if (c.p.geometry == MFL_GEOM_CURVED) {
@@ -252,11 +375,44 @@ hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStrea
   if (e != hipSuccess) return e;
   const double amp = c.p.geometry == MFL_GEOM_CURVED ? c.p.curve_amp : 0.0;
 #define CASE(K)                                                                              \
-  rhs_kernel<K><<<int(L.ncells), kBlock, 0, s>>>(b, L.Nc, L.N1, L.h, amp,                     \
-                                                  shrink_tab<K + 1, double>(c.tab64));        \
+  rhs_kernel<K, SineForcing><<<int(L.ncells), kBlock, 0, s>>>(                                \
+      b, L.Nc, L.N1, L.h, c.p.domain_lo, amp, dirichlet_mask(c.p), shrink_tab<K + 1, double>(c.tab64)); \
   break
   MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_gaussians(const Context &c, const Level &L, double *b, hipStream_t s) {
+  hipError_t e = launch_fill(b, MFL_F64, L.ndofs, 0.0, s);
+  if (e != hipSuccess) return e;
+  const int dm = dirichlet_mask(c.p);
+  const int64_t faces = 6 * int64_t(L.Nc) * L.Nc;
+#define CASE(K)                                                                              \
+  rhs_kernel<K, GaussianForcing><<<int(L.ncells), kBlock, 0, s>>>(                            \
+      b, L.Nc, L.N1, L.h, c.p.domain_lo, 0.0, dm, shrink_tab<K + 1, double>(c.tab64));        \
+  neumann_face_kernel<K><<<int(faces), kBlock, 0, s>>>(b, L.Nc, L.N1, L.h, c.p.domain_lo, dm, \
+                                                       shrink_tab<K + 1, double>(c.tab64));   \
+  break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_gaussian_dirichlet(const Context &c, const Level &L, double *x0, hipStream_t s) {
+  const int dm = dirichlet_mask(c.p);
+#define CASE(K)                                                                              \
+  gaussian_dirichlet_kernel<K><<<grid_for(L.ndofs, 16384), kBlock, 0, s>>>(                   \
+      x0, L.Nc, L.N1, L.h, c.p.domain_lo, dm, shrink_tab<K + 1, double>(c.tab64));             \
+  break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_lift(const Context &c, const Level &L, double *b, const double *x0, const double *a0,
+                       hipStream_t s) {
+  lift_kernel<<<grid_for(L.ndofs, 16384), kBlock, 0, s>>>(b, x0, a0, L.N1, dirichlet_mask(c.p));
   return hipGetLastError();
 }
 

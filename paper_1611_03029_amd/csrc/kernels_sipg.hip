@@ -30,7 +30,7 @@ constexpr int kBlock = 256;
 // derivative = own derivative), or homogeneous Neumann (no contribution).
 template <int N, typename T>
 __device__ __forceinline__ void sipg_line(const ct::DGTab<N, T> &tb, const T *u, const T *uL, bool hasL,
-                                          const T *uR, bool hasR, T inv_h, T sigma, int dirichlet,
+                                          const T *uR, bool hasR, T inv_h, T sigma, int dmask,
                                           T scale, T *out) {
   T t[N];
   eo_apply<N, 1>(tb.Kg, u, t);
@@ -58,7 +58,7 @@ __device__ __forceinline__ void sipg_line(const ct::DGTab<N, T> &tb, const T *u,
     if (has) {
       jump = vm - vp;
       avg = T(0.5) * sign * (dm + dp) * inv_h;
-    } else if (dirichlet) {
+    } else if ((dmask >> s) & 1) {
       jump = T(2) * vm;
       avg = sign * dm * inv_h;
     } else {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void sipg_line(const ct::DGTab<N, T> &tb, const T *u,
 
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
-sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma, int dirichlet) {
+sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma, int dmask) {
   constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = kBlock / n2;
   constexpr const ct::DGTab<n, T> &tb = ct::DGTables<n, T>::tab;
   __shared__ T U[CPB * n3], R[CPB * n3];
@@ -115,7 +115,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
       ul[l] = (active && hasL) ? pl[l * n2 + p] : T(0);
       ur[l] = (active && hasR) ? pr[l * n2 + p] : T(0);
     }
-    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dirichlet, scale, out);
+    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       Uc[l * n2 + p] = u[l];
@@ -135,7 +135,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
       ul[b] = (active && hasL) ? pl[o] : T(0);
       ur[b] = (active && hasR) ? pr[o] : T(0);
     }
-    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dirichlet, scale, out);
+    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
 #pragma unroll
     for (int b = 0; b < n; ++b) Rc[i1 * n2 + b * n + i0] += out[b];
   }
@@ -152,7 +152,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
       ul[a] = (active && hasL) ? pl[o] : T(0);
       ur[a] = (active && hasR) ? pr[o] : T(0);
     }
-    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dirichlet, scale, out);
+    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
     if (active) {
       T *d = dst + cell * n3 + i1 * n2 + i0 * n;
 #pragma unroll
@@ -167,7 +167,7 @@ hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStr
   const int grid = int((L.ncells + CPB - 1) / CPB);
   const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
   sipg_kernel<K, T><<<grid, kBlock, 0, s>>>(src, dst, L.Nc, T(L.h), T(sigma),
-                                           c.p.bc == MFL_BC_DIRICHLET);
+                                           dirichlet_mask(c.p));
   return hipGetLastError();
 }
 

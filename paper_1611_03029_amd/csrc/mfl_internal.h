@@ -23,7 +23,7 @@ constexpr int kReduceBlocks = 1024;         // partial sums of the vector reduct
 //   D [q n + p] : derivative of Gauss-Lagrange basis p at Gauss point q (collocation)
 //   M, K        : reference [0,1] mass and stiffness matrices of the GLL basis
 //   Fv, Fd      : Gauss-Lagrange basis p and its derivative at xi = 0 (p) and xi = 1 (n + p)
-//   w, gll      : Gauss weights, GLL nodes on [0,1]
+//   w, gll, xg  : Gauss weights, GLL nodes, Gauss points on [0,1]
 template <int N, typename T>
 struct Tab {
   T S[N * N];
@@ -35,6 +35,7 @@ struct Tab {
   T Fd[2 * N];
   T w[N];
   T gll[N];
+  T xg[N];
 };
 
 // Even-odd form of an N x N matrix A that is centro-symmetric (A[N-1-q][N-1-i] = A[q][i])
@@ -121,6 +122,12 @@ struct Context {
   std::vector<hipEvent_t> prof_start, prof_stop;
 };
 
+// Face mask of the Dirichlet conditions: bit 0 the lower faces (x_e = domain_lo), bit 1
+// the upper faces (x_e = domain_lo + domain_len).
+inline int dirichlet_mask(const mfl_params &p) {
+  return p.bc == MFL_BC_DIRICHLET ? 3 : (p.bc == MFL_BC_MIXED ? 2 : 0);
+}
+
 enum Scalar { kRZ = 0, kPQ, kAlpha, kBeta, kRR, kBB, kRZnew, kNumScalars = 16 };
 
 // ---- host-side tables -------------------------------------------------------
@@ -133,15 +140,25 @@ void build_tables(int k, Tab<kMaxN, double> &t64, Tab<kMaxN, float> &t32, Transf
 hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
                                 void *dst, hipStream_t s);
 // CG operator: brick kernel (owned DoFs + halo records), then the halo addition
+// (dmask < 0: the Dirichlet faces of the parameters; 0: the operator without boundary
+// conditions, used for the lifting of Dirichlet data)
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
-                           hipStream_t s);
-hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s);
+                           hipStream_t s, int dmask = -1);
+hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s,
+                              int dmask = -1);
 int64_t cg_halo_elements(int k, int Nc);
 hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *u, const double *lam,
                                 double *grad, hipStream_t s);
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s);
 hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s);
 hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStream_t s);
+// right-hand side of the three-Gaussian example: forcing and Neumann loads (b = 0 first)
+hipError_t launch_rhs_gaussians(const Context &c, const Level &L, double *b, hipStream_t s);
+// x0 = the solution of the three-Gaussian example on the Dirichlet DoFs, 0 elsewhere
+hipError_t launch_gaussian_dirichlet(const Context &c, const Level &L, double *x0, hipStream_t s);
+// b = x0 on Dirichlet DoFs, b - a0 elsewhere
+hipError_t launch_lift(const Context &c, const Level &L, double *b, const double *x0, const double *a0,
+                       hipStream_t s);
 hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
                              hipStream_t s);
 
@@ -169,9 +186,9 @@ hipError_t launch_pcg_update_xr(double *x, double *r, const double *p, const dou
                                 const double *scalars, int64_t n, double *partials, hipStream_t s);
 hipError_t launch_pcg_update_p(double *p, const double *z, const double *scalars, int64_t n,
                                hipStream_t s);
-hipError_t launch_random_start(double *v, const Level &L, uint64_t key, hipStream_t s);
+hipError_t launch_random_start(double *v, const Level &L, uint64_t key, int dmask, hipStream_t s);
 hipError_t launch_jacobi(const double *dinv, const double *r, double *z, int64_t n, hipStream_t s);
-hipError_t launch_zero_boundary(double *v, const Level &L, hipStream_t s);
+hipError_t launch_zero_boundary(double *v, const Level &L, int dmask, hipStream_t s);
 
 // finalize ops
 enum FinalizeOp { kFinSum = 0, kFinAlpha = 1, kFinBeta = 2 };

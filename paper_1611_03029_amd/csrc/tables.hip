@@ -110,6 +110,7 @@ void build_tables(int k, Tab<kMaxN, double> &t, Tab<kMaxN, float> &t32, Transfer
     for (int p = 0; p < n; ++p) t.D[q * n + p] = d[p];
     t.w[q] = wq[q];
     t.gll[q] = xl[q];
+    t.xg[q] = xq[q];
   }
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {

@@ -16,6 +16,7 @@ SEED_SIPG_Q5 = 4           # SIPG Q5, 32^3 cells
 SEED_KAPPA_FIELD = 5       # log-diffusivity field g
 SEED_KAPPA_PERTURB = 6     # perturbation that defines the target state
 SEED_FD_CELLS = 7          # cells probed by finite differences
+SEED_MIXED_BC = 8          # apply inputs with mixed boundary conditions on (-1,1)^3
 
 
 def uniform_vector(n, seed, dtype=np.float64):

@@ -52,13 +52,16 @@ def test_workspace_scales_with_geometry_and_multigrid():
 
 
 @pytest.mark.parametrize("kw", [dict(degree=0), dict(degree=9), dict(cells_per_dim=0),
-                                dict(disc=2), dict(geometry=5), dict(bc=3), dict(mg_precision=7),
+                                dict(disc=2), dict(geometry=5), dict(bc=3), dict(bc=-1), dict(mg_precision=7),
                                 dict(disc=mfl.SIPG, geometry=mfl.CURVED),
                                 dict(disc=mfl.SIPG, build_mg=True),
                                 dict(cells_per_dim=12, build_mg=True, min_level_cells=2),
                                 dict(build_mg=True, bc=mfl.NEUMANN),
                                 dict(geometry=mfl.CURVED, curve_amp=0.5),
-                                dict(build_mg=True, cheb_lo=1.5)])
+                                dict(build_mg=True, cheb_lo=1.5),
+                                dict(domain_len=0.0), dict(domain_len=-2.0),
+                                dict(domain_lo=float("nan")),
+                                dict(geometry=mfl.CURVED, domain_lo=-1.0, domain_len=2.0)])
 def test_invalid_params_rejected(kw):
     base = dict(degree=2, cells_per_dim=8)
     base.update(kw)
@@ -83,3 +86,11 @@ def test_setup_rejects_null_workspace_without_gpu():
 def test_null_handle_rejected():
     assert mfl.lib().mfl_apply(None, -1, 0, None, None, None) == _mfl.MFL_EINVAL
     assert mfl.lib().mfl_destroy(None) == _mfl.MFL_EINVAL
+
+
+def test_mixed_conditions_and_domain_accepted():
+    n, c, ws = mfl.query(mfl.make_params(3, 8, bc=mfl.MIXED, build_mg=True, domain_lo=-1.0,
+                                         domain_len=2.0))
+    assert n == 25 ** 3 and c == 512 and ws > 0
+    n2, _, ws2 = mfl.query(mfl.make_params(3, 8, bc=mfl.MIXED, disc=mfl.SIPG))
+    assert n2 == 512 * 64 and ws2 > 0
