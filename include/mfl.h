@@ -97,7 +97,8 @@ int mfl_default_params(mfl_params *p);
  * level, and the workspace size in bytes that mfl_setup needs.  Any output may be NULL.
  * Errors: MFL_EINVAL for an unsupported or inconsistent p (k outside 1..8, N_c not
  * reducible by halving to min_level_cells when build_mg = 1, SIPG with curved
- * geometry or multigrid). */
+ * geometry, multigrid with Neumann conditions on every face, a curved mesh off the unit
+ * cube). */
 int mfl_query(const mfl_params *p, int64_t *n_dofs, int64_t *n_cells, int64_t *workspace_bytes);
 
 /* Build the level hierarchy in `workspace` (device memory, >= the queried size, 256-byte
@@ -131,12 +132,13 @@ int mfl_level_info(mfl_handle h, int level, int *cells_per_dim, int64_t *n_dofs,
  * overlap.  Asynchronous. */
 int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, void *stream);
 
-/* out = diag(A) on `level` (-1 = finest), in dtype (CG only; Dirichlet DoFs hold 1). */
+/* out = diag(A) on `level` (-1 = finest), in dtype (CG: Dirichlet DoFs hold 1). */
 int mfl_diagonal(mfl_handle h, int level, int dtype, void *out, void *stream);
 
 /* Transfer between level l-1 (coarse) and l (fine), in the multigrid precision dtype:
  * direction 0: fine += P coarse (embedding, Sec. 4.1); direction 1: coarse = P^T fine.
- * Dirichlet rows/columns of P are removed.  Asynchronous. */
+ * CG: Dirichlet rows/columns of P are removed.  SIPG: the coarse cell's polynomial
+ * evaluated at the Gauss points of its 8 children (block diagonal).  Asynchronous. */
 int mfl_transfer(mfl_handle h, int level, int direction, int dtype, const void *src, void *dst,
                  void *stream);
 
@@ -169,7 +171,10 @@ int mfl_rhs_sine(mfl_handle h, double *b, void *stream);
  * the Dirichlet faces (0 elsewhere), A0 = the operator without boundary conditions.  The
  * solution of A x = b then carries the Dirichlet data.  b: device, n_dofs doubles.
  * Uses the handle's work vectors (not concurrently with a solve on the same handle).
- * Errors: MFL_EUNSUPPORTED for SIPG or curved meshes.  Asynchronous. */
+ * SIPG (Gauss-point basis): b_i = (f, psi_i) plus the data terms of the mirror extension
+ * of eq. (bc_dgsip): int (2 sigma g_D psi_i - g_D n . grad psi_i) on Dirichlet faces and
+ * int (grad u . n) psi_i on Neumann faces.
+ * Errors: MFL_EUNSUPPORTED for curved meshes.  Asynchronous. */
 int mfl_rhs_gaussians(mfl_handle h, double *b, void *stream);
 
 int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double rtol, int maxit,

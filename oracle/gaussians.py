@@ -23,7 +23,7 @@ Test infrastructure only: used by the tests, never by the library.
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from . import cg
+from . import cg, sipg
 from .basis import gauss_legendre, lagrange_values
 from .mesh import Box
 
@@ -129,3 +129,22 @@ def solve_direct(Nc, k, bc="mixed"):
 def relative_l2_error(box, u):
     """|| u_h - u ||_{L2} / || u ||_{L2} with k+3 Gauss points per direction."""
     return cg.l2_error(box, u, exact=solution) / cg.l2_norm(box, solution)
+
+
+# ---- DG-SIP discretization of the same example ----------------------------------------
+# The paper's penalty sigma = (k+1)^2 d / h, i.e. c_pen = 3 in sipg.DGBox.
+
+def dg_box(cells_per_dim, degree, c_pen=3.0):
+    return sipg.DGBox(cells_per_dim, degree, c_pen=c_pen, lo=-1.0, length=2.0)
+
+
+def dg_rhs(dg, bc="mixed"):
+    """(f, v) plus the boundary data terms of eq. (bc_dgsip) (sipg.boundary_data_load)."""
+    return sipg.rhs(dg, forcing) + sipg.boundary_data_load(
+        dg, solution, lambda x, nrm: gradient(x) @ nrm, bc)
+
+
+def dg_solve_direct(Nc, k, bc="mixed", c_pen=3.0):
+    dg = dg_box(Nc, k, c_pen)
+    A = sipg.assemble(dg, bc)
+    return dg, spla.spsolve(A.tocsc(), dg_rhs(dg, bc))

@@ -1,4 +1,4 @@
-"""Symmetric interior penalty DG Laplacian on Cartesian meshes of the unit cube.
+"""Symmetric interior penalty DG Laplacian on Cartesian meshes of a cube.
 
 Section 2.2, eq. (poisson_dgsip): with kappa = 1,
 
@@ -8,8 +8,13 @@ Section 2.2, eq. (poisson_dgsip): with kappa = 1,
 where <.,.>_dT runs over all faces of every cell, so each interior face is seen
 from both sides with the outward normal n of the cell whose test function v is
 used.  Eq. (bc_dgsip) gives the exterior values on the boundary:
-Dirichlet u^+ = -u^-, grad u^+ = grad u^- (homogeneous data);
-Neumann u^+ = u^-, grad u^+ . n = -grad u^- . n (homogeneous data).
+Dirichlet u^+ = -u^- + 2 g_D, grad u^+ = grad u^-;
+Neumann u^+ = u^-, grad u^+ . n = -grad u^- . n - 2 g_N (kappa = 1), with the paper's
+g_N = -n . grad u the outward flux.  The operator holds the terms in the unknowns; the
+data terms go to the right-hand side (boundary_data_load): on a Dirichlet face
+int (2 sigma g_D v - g_D n . grad v), on a Neumann face int (n . grad u) v.
+Which faces are Dirichlet is given as in mesh.Box: 'dirichlet' (all), 'neumann' (none),
+'mixed' (the upper faces x_e = lo + length) or a face mask.
 
 The penalty is sigma = c_pen (k+1)^2 / h; the paper's choice (k+1)^2 d / h is
 c_pen = d = 3.  The basis is the Lagrange basis in the k+1 Gauss-Legendre points of
@@ -29,11 +34,15 @@ from .cg import reference_tables, tensor_weights
 
 
 class DGBox:
-    def __init__(self, cells_per_dim, degree, c_pen=1.0):
+    """N_c^3 Cartesian cells of [lo, lo + length]^3 carrying the DG Q_k space."""
+
+    def __init__(self, cells_per_dim, degree, c_pen=1.0, lo=0.0, length=1.0):
         self.Nc = int(cells_per_dim)
         self.k = int(degree)
         self.n = self.k + 1
-        self.h = 1.0 / self.Nc
+        self.lo = float(lo)
+        self.length = float(length)
+        self.h = self.length / self.Nc
         self.c_pen = float(c_pen)
         self.sigma = self.c_pen * (self.k + 1) ** 2 / self.h
         self.n_cells = self.Nc ** 3
@@ -105,7 +114,9 @@ def face_blocks(dg):
 
 
 def assemble(dg, bc="dirichlet"):
-    """CSR matrix of the SIPG operator (bc: 'dirichlet' or 'neumann')."""
+    """CSR matrix of the SIPG operator (bc: name or face mask of the Dirichlet faces)."""
+    from .mesh import bc_mask
+    m = bc_mask(bc)
     n3 = dg.n ** 3
     Ac = cell_matrix(dg)
     blocks = face_blocks(dg)
@@ -122,10 +133,8 @@ def assemble(dg, bc="dirichlet"):
                 rows.append(e * n3 + R)
                 cols.append(f * n3 + Cc)
                 vals.append(nbr.ravel())
-            elif bc == "dirichlet":
+            elif m & (1 << s):
                 acc_own += dirichlet
-            elif bc != "neumann":
-                raise ValueError(bc)
         rows.append(e * n3 + R)
         cols.append(e * n3 + Cc)
         vals.append(acc_own.ravel())
@@ -137,6 +146,8 @@ def assemble(dg, bc="dirichlet"):
 
 def apply_rows(dg, u, rows, bc="dirichlet"):
     """(A u)[rows], computed from the cell's own block and its six face blocks."""
+    from .mesh import bc_mask
+    m = bc_mask(bc)
     n3 = dg.n ** 3
     Ac = cell_matrix(dg)
     blocks = face_blocks(dg)
@@ -149,7 +160,7 @@ def apply_rows(dg, u, rows, bc="dirichlet"):
             f = dg.neighbor(e, d, s)
             if f >= 0:
                 acc += own[i] @ ue + nbr[i] @ u[f * n3:(f + 1) * n3]
-            elif bc == "dirichlet":
+            elif m & (1 << s):
                 acc += dirichlet[i] @ ue
         y[t] = acc
     return y
@@ -163,8 +174,8 @@ def cell_points(dg):
     lx = np.tile(dg.nodes, n * n)
     ly = np.tile(np.repeat(dg.nodes, n), n)
     lz = np.repeat(dg.nodes, n * n)
-    return np.stack([(cx[:, None] + lx) * dg.h, (cy[:, None] + ly) * dg.h,
-                     (cz[:, None] + lz) * dg.h], axis=-1)
+    return dg.lo + np.stack([(cx[:, None] + lx) * dg.h, (cy[:, None] + ly) * dg.h,
+                             (cz[:, None] + lz) * dg.h], axis=-1)
 
 
 def rhs(dg, f):
@@ -183,8 +194,47 @@ def l2_error(dg, u, exact, extra_points=2):
     n = dg.n + extra_points
     c = np.arange(dg.n_cells)
     cx, cy, cz = c % dg.Nc, (c // dg.Nc) % dg.Nc, c // (dg.Nc * dg.Nc)
-    P = np.stack([(cx[:, None] + np.tile(xq, n * n)) * dg.h,
-                  (cy[:, None] + np.tile(np.repeat(xq, n), n)) * dg.h,
-                  (cz[:, None] + np.repeat(xq, n * n)) * dg.h], axis=-1)
+    P = dg.lo + np.stack([(cx[:, None] + np.tile(xq, n * n)) * dg.h,
+                          (cy[:, None] + np.tile(np.repeat(xq, n), n)) * dg.h,
+                          (cz[:, None] + np.repeat(xq, n * n)) * dg.h], axis=-1)
     uh = u.reshape(dg.n_cells, -1) @ val.T
     return float(np.sqrt(np.sum(w3[None, :] * (uh - exact(P)) ** 2)))
+
+
+def boundary_data_load(dg, g_dirichlet, flux, bc="mixed"):
+    """Right-hand side terms of the boundary data: on the Dirichlet faces of `bc`
+    int (2 sigma g_D v - g_D n . grad v), on the other boundary faces int flux v, where
+    g_dirichlet(x) and flux(x, normal) = n . grad u are evaluated at the (k+1)^2 Gauss
+    points of each boundary face."""
+    from .mesh import bc_mask
+    m = bc_mask(bc)
+    n3 = dg.n ** 3
+    W = np.kron(dg.weights, dg.weights) * dg.h ** 2
+    b = np.zeros(dg.n_dofs)
+    Nc = dg.Nc
+    c = np.arange(dg.n_cells)
+    cc = [c % Nc, (c // Nc) % Nc, c // (Nc * Nc)]
+    for d in range(3):
+        tang = [a for a in range(3) if a != d]
+        for s in (0, 1):
+            sign = 1.0 if s == 1 else -1.0
+            V, G = face_tables(dg.nodes, dg.nodes, d, float(s))
+            Dn = sign * G / dg.h
+            cells = c[cc[d] == (Nc - 1 if s else 0)]
+            # face points: normal coordinate on the face, tangential at the Gauss points
+            t1 = np.tile(dg.nodes, dg.n)
+            t2 = np.repeat(dg.nodes, dg.n)
+            X = np.zeros((len(cells), dg.n * dg.n, 3))
+            X[:, :, d] = dg.lo + (cc[d][cells][:, None] + s) * dg.h
+            X[:, :, tang[0]] = dg.lo + (cc[tang[0]][cells][:, None] + t1[None, :]) * dg.h
+            X[:, :, tang[1]] = dg.lo + (cc[tang[1]][cells][:, None] + t2[None, :]) * dg.h
+            normal = np.zeros(3)
+            normal[d] = sign
+            if m & (1 << s):
+                g = g_dirichlet(X)
+                be = (2.0 * dg.sigma * (W[None, :] * g)) @ V - (W[None, :] * g) @ Dn
+            else:
+                be = (W[None, :] * flux(X, normal)) @ V
+            for j, e in enumerate(cells):
+                b[e * n3:(e + 1) * n3] += be[j]
+    return b

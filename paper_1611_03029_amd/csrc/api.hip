@@ -53,7 +53,6 @@ int check_params(const mfl_params *p) {
   if (p->disc == MFL_DISC_SIPG) {
     if (p->geometry != MFL_GEOM_CARTESIAN)
       return fail(MFL_EINVAL, "SIPG is implemented on Cartesian meshes only");
-    if (p->build_mg) return fail(MFL_EINVAL, "multigrid is implemented for the CG discretization only");
     if (!(p->penalty_factor > 0.0)) return fail(MFL_EINVAL, "penalty_factor must be > 0");
   }
   if (p->geometry == MFL_GEOM_CURVED) {
@@ -117,8 +116,8 @@ int64_t layout(Context &c, char *base) {
       L.metric64 = b.take<double>(L.ncells * 6 * n3);
       L.metric32 = b.take<float>(L.ncells * 6 * n3);
     }
-    if (cg) {
-      L.halo = b.take<double>(cg_halo_elements(c.k, L.Nc));
+    if (cg) L.halo = b.take<double>(cg_halo_elements(c.k, L.Nc));
+    {
       L.diag64 = b.take<double>(L.ndofs);
       L.dinv64 = b.take<double>(L.ndofs);
       L.diag32 = b.take<float>(L.ndofs);
@@ -234,6 +233,10 @@ int read_scalars(Context &c, hipStream_t s) {
   return MFL_OK;
 }
 
+// Faces whose DoFs are identity rows of the operator: the Dirichlet faces for CG; none for
+// SIPG, which imposes Dirichlet data weakly.
+int row_mask(const Context &c) { return c.p.disc == MFL_DISC_CG ? dirichlet_mask(c.p) : 0; }
+
 // Jacobi-preconditioned CG on level l from the SplitMix64 start vector (key = cells per
 // direction, Dirichlet entries zero); records the Lanczos tridiagonal from alpha, beta.
 int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vector<double> &diag,
@@ -241,7 +244,7 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
   Level &L = c.levels[l];
   const int64_t N = L.ndofs;
   double *r = c.r, *z = c.z, *p = c.pv, *q = c.q;
-  HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), dirichlet_mask(c.p), s));
+  HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), row_mask(c), s));
   HIP_TRY(launch_jacobi(L.dinv64, r, z, N, s));
   HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
@@ -282,8 +285,12 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
 int rebuild_kappa_dependent(Context &c, hipStream_t s) {
   const int nl = int(c.levels.size());
   for (int l = nl - 2; l >= 0; --l) HIP_TRY(launch_coarsen_kappa(c.levels[l], c.levels[l + 1], s));
-  if (c.p.disc != MFL_DISC_CG) return MFL_OK;
-  for (int l = 0; l < nl; ++l) HIP_TRY(launch_cg_diagonal(c, c.levels[l], s));
+  for (int l = 0; l < nl; ++l) {
+    if (c.p.disc == MFL_DISC_CG)
+      HIP_TRY(launch_cg_diagonal(c, c.levels[l], s));
+    else
+      HIP_TRY(launch_sipg_diagonal(c, c.levels[l], s));
+  }
   if (!c.p.build_mg) {
     HIP_TRY(hipStreamSynchronize(s));
     return MFL_OK;
@@ -294,9 +301,10 @@ int rebuild_kappa_dependent(Context &c, hipStream_t s) {
     double lmin, lmax;
     int rc;
     if (l == 0) {
-      // unknowns without Dirichlet conditions: N1 - (number of Dirichlet faces) per direction
-      const int dm = dirichlet_mask(c.p), m1 = L.N1 - (dm & 1) - ((dm >> 1) & 1);
-      const int interior = m1 * m1 * m1;
+      // unknowns: CG without the Dirichlet DoFs (N1 minus the number of Dirichlet faces
+      // per direction); SIPG all DoFs
+      const int dm = row_mask(c), m1 = L.N1 - (dm & 1) - ((dm >> 1) & 1);
+      const int interior = c.p.disc == MFL_DISC_CG ? m1 * m1 * m1 : int(L.ndofs);
       if ((rc = lanczos(c, l, interior + 50, true, a, b, s))) return rc;
       tridiag_extremes(a, b, lmin, lmax);
       L.coarse_lmin = lmin;
@@ -350,6 +358,19 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
   return MFL_OK;
 }
 
+// Transfers between level l-1 and level l of the discretization in use.
+hipError_t restrict_to(Context &c, int l, const void *bf, const void *axf, int fd, void *bc, int cd,
+                       hipStream_t s) {
+  if (c.p.disc == MFL_DISC_CG)
+    return launch_restrict_residual(c, c.levels[l - 1], c.levels[l], bf, axf, fd, bc, cd, s);
+  return launch_dg_restrict(c, c.levels[l - 1], bf, axf, fd, bc, cd, s);
+}
+
+hipError_t prolongate_from(Context &c, int l, const void *xc, int cd, void *xf, int fd, hipStream_t s) {
+  if (c.p.disc == MFL_DISC_CG) return launch_prolongate_add(c, c.levels[l - 1], c.levels[l], xc, cd, xf, fd, s);
+  return launch_dg_prolongate_add(c, c.levels[l - 1], xc, cd, xf, fd, s);
+}
+
 // One V(1,1) cycle on level l; the right-hand side is b_in (level-0 and recursion: L.b).
 int cycle(Context &c, int l, const void *b_in, int b_dtype, double *x64_out, hipStream_t s) {
   Level &L = c.levels[l];
@@ -362,9 +383,9 @@ int cycle(Context &c, int l, const void *b_in, int b_dtype, double *x64_out, hip
   Level &C = c.levels[l - 1];
   if ((rc = chebyshev(c, l, lo, hi, updates, true, b_in, b_dtype, nullptr, s))) return rc;
   if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
-  HIP_TRY(launch_restrict_residual(c, C, L, L.b, L.ax, dt, C.b, dtype_of(C), s));
+  HIP_TRY(restrict_to(c, l, L.b, L.ax, dt, C.b, dtype_of(C), s));
   if ((rc = cycle(c, l - 1, C.b, dtype_of(C), nullptr, s))) return rc;
-  HIP_TRY(launch_prolongate_add(c, C, L, C.x, dtype_of(C), L.x, dt, s));
+  HIP_TRY(prolongate_from(c, l, C.x, dtype_of(C), L.x, dt, s));
   return chebyshev(c, l, lo, hi, updates, false, nullptr, dt, x64_out, s);
 }
 
@@ -572,7 +593,6 @@ int mfl_profile(mfl_handle h, int enable, int *launches, double *total_ms) {
 
 int mfl_diagonal(mfl_handle h, int level, int dtype, void *out, void *stream) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
-  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "diagonal is implemented for CG only");
   const int l = level_index(*h, level);
   if (l < 0) return fail(MFL_EINVAL, "level %d out of range", level);
   if (!out) return fail(MFL_EINVAL, "out is NULL");
@@ -590,7 +610,6 @@ int mfl_diagonal(mfl_handle h, int level, int dtype, void *out, void *stream) {
 int mfl_transfer(mfl_handle h, int level, int direction, int dtype, const void *src, void *dst,
                  void *stream) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
-  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "transfer is implemented for CG only");
   const int l = level_index(*h, level);
   if (l < 1) return fail(MFL_EINVAL, "transfer needs a level >= 1 (got %d)", level);
   if (dtype != MFL_F64 && dtype != MFL_F32) return fail(MFL_EINVAL, "unknown dtype %d", dtype);
@@ -598,9 +617,9 @@ int mfl_transfer(mfl_handle h, int level, int direction, int dtype, const void *
   const int cdt = (l - 1 == 0) ? MFL_F64 : dtype;
   hipStream_t s = as_stream(stream);
   if (direction == 0)
-    HIP_TRY(launch_prolongate_add(*h, h->levels[l - 1], h->levels[l], src, cdt, dst, dtype, s));
+    HIP_TRY(prolongate_from(*h, l, src, cdt, dst, dtype, s));
   else if (direction == 1)
-    HIP_TRY(launch_restrict_residual(*h, h->levels[l - 1], h->levels[l], src, nullptr, dtype, dst, cdt, s));
+    HIP_TRY(restrict_to(*h, l, src, nullptr, dtype, dst, cdt, s));
   else
     return fail(MFL_EINVAL, "direction must be 0 (prolongate) or 1 (restrict)");
   return MFL_OK;
@@ -632,12 +651,15 @@ int mfl_rhs_sine(mfl_handle h, double *b, void *stream) {
 
 int mfl_rhs_gaussians(mfl_handle h, double *b, void *stream) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
-  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "the three-Gaussian right-hand side is CG only");
   if (h->p.geometry != MFL_GEOM_CARTESIAN)
     return fail(MFL_EUNSUPPORTED, "the three-Gaussian right-hand side needs a Cartesian mesh");
   if (!b) return fail(MFL_EINVAL, "b is NULL");
   hipStream_t s = as_stream(stream);
   const Level &F = h->levels.back();
+  if (h->p.disc == MFL_DISC_SIPG) {
+    HIP_TRY(launch_sipg_rhs_gaussians(*h, F, b, s));
+    return MFL_OK;
+  }
   // forcing and Neumann loads into b; x0 = Dirichlet data in r; z = A0 x0 (operator
   // without boundary conditions); then b = x0 on Dirichlet DoFs and b - z elsewhere
   HIP_TRY(launch_rhs_gaussians(*h, F, b, s));
@@ -652,6 +674,7 @@ int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double r
                       int *iters, double *final_rel_res, void *stream) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
   if (!need_mg(*h)) return fail(MFL_EINVAL, "handle was set up without multigrid (build_mg = 0)");
+  if (h->p.disc != MFL_DISC_CG) return fail(MFL_EUNSUPPORTED, "the adjoint solve is CG only");
   if (!dJdu || !lambda) return fail(MFL_EINVAL, "dJdu/lambda is NULL");
   if (!(rtol > 0.0) || maxit < 1) return fail(MFL_EINVAL, "need rtol > 0 and maxit >= 1");
   hipStream_t s = as_stream(stream);

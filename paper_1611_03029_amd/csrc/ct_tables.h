@@ -162,14 +162,16 @@ struct Tables {
   static constexpr EOTab<N, T> eo = eotab<N, T>();
 };
 
-// DG basis (Lagrange in the N Gauss points of [0,1]): Gauss weights w, reference stiffness
-// Kg[i][j] = sum_q w_q psi_i'(x_q) psi_j'(x_q) in even-odd form, and the basis values and
-// derivatives at the end points: fv0[i] = psi_i(0), fd0[i] = psi_i'(0).  By the symmetry of
-// the points, psi_i(1) = fv0[N-1-i] and psi_i'(1) = -fd0[N-1-i].
+// DG basis (Lagrange in the N Gauss points of [0,1]): Gauss points xg and weights w,
+// reference stiffness Kg[i][j] = sum_q w_q psi_i'(x_q) psi_j'(x_q) in even-odd form and its
+// diagonal kgd, and the basis values and derivatives at the end points: fv0[i] = psi_i(0),
+// fd0[i] = psi_i'(0).  By the symmetry of the points, psi_i(1) = fv0[N-1-i] and
+// psi_i'(1) = -fd0[N-1-i].
 template <int N, typename T>
 struct DGTab {
-  T w[N];
+  T xg[N], w[N];
   T fv0[N], fd0[N];
+  T kgd[N];
   EO<N, T> Kg;
 };
 
@@ -187,7 +189,9 @@ constexpr DGTab<N, T> dgtab() {
       Kg[i * N + j] = s;
     }
   for (int i = 0; i < N; ++i) {
+    t.xg[i] = T(r.xg[i]);
     t.w[i] = T(r.wg[i]);
+    t.kgd[i] = T(Kg[i * N + i]);
     const LegVal v = lagrange<N>(r.xg, i, 0.0);
     t.fv0[i] = T(v.P);
     t.fd0[i] = T(v.dP);

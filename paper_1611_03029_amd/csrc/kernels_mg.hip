@@ -62,6 +62,18 @@ diag_finalize_kernel(double *__restrict__ d64, double *__restrict__ i64, float *
   }
 }
 
+// Inverse and FP32 copies of a diagonal without identity rows (SIPG).
+__global__ void __launch_bounds__(kBlock)
+diag_invert_kernel(const double *__restrict__ d64, double *__restrict__ i64, float *__restrict__ d32,
+                   float *__restrict__ i32, int64_t n) {
+  GRID_STRIDE(i, n) {
+    const double v = d64[i];
+    i64[i] = 1.0 / v;
+    d32[i] = float(v);
+    i32[i] = float(1.0 / v);
+  }
+}
+
 // First Chebyshev update from a zero initial guess: d = D^{-1} b / theta, x = d.
 // b_in may be of another precision than the level (the FP64 residual entering an FP32
 // cycle); it is stored converted in b_store for the residuals of the later steps.
@@ -252,16 +264,16 @@ pcg_update_p_kernel(double *__restrict__ p, const double *__restrict__ z, const 
 // SplitMix64 counter stream (Steele, Lea, Flood 2014): value i of stream `key` is the
 // finalizer applied to key + (i+1) * 0x9E3779B97F4A7C15, mapped to [-1, 1).
 __global__ void __launch_bounds__(kBlock)
-random_start_kernel(double *__restrict__ v, int N1, uint64_t key, int dmask) {
-  const int64_t n = int64_t(N1) * N1 * N1;
+random_start_kernel(double *__restrict__ v, int64_t n, int N1, uint64_t key, int dmask) {
   GRID_STRIDE(i, n) {
     uint64_t z = key + uint64_t(i + 1) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z = z ^ (z >> 31);
     const double u = 2.0 * double(z >> 11) * 0x1.0p-53 - 1.0;
+    // dmask = 0 (no Dirichlet rows, e.g. the DG layout): the grid coordinates are unused
     const int x = int(i % N1), y = int((i / N1) % N1), zz = int(i / (int64_t(N1) * N1));
-    const bool bnd = dirichlet_dof(x, y, zz, N1, dmask);
+    const bool bnd = dmask != 0 && dirichlet_dof(x, y, zz, N1, dmask);
     v[i] = bnd ? 0.0 : u;
   }
 }
@@ -312,6 +324,11 @@ hipError_t launch_coarsen_kappa(const Level &coarse, const Level &fine, hipStrea
 hipError_t launch_diag_finalize(const Context &c, const Level &L, hipStream_t s) {
   diag_finalize_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(L.diag64, L.dinv64, L.diag32, L.dinv32,
                                                             L.N1, dirichlet_mask(c.p));
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_invert(const Level &L, hipStream_t s) {
+  diag_invert_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(L.diag64, L.dinv64, L.diag32, L.dinv32, L.ndofs);
   return hipGetLastError();
 }
 
@@ -425,7 +442,7 @@ hipError_t launch_pcg_update_p(double *p, const double *z, const double *scalars
 }
 
 hipError_t launch_random_start(double *v, const Level &L, uint64_t key, int dmask, hipStream_t s) {
-  random_start_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.N1, key, dmask);
+  random_start_kernel<<<grid_for(L.ndofs), kBlock, 0, s>>>(v, L.ndofs, L.N1, key, dmask);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 // XCD).  Every DoF is written once by its own cell: no atomics.
 #include "ct_tables.h"
 #include "device_common.h"
+#include "gaussians.h"
 
 namespace mfl {
 
@@ -171,6 +172,182 @@ hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStr
   return hipGetLastError();
 }
 
+// Own-cell diagonal of the 1D line operator at index a for a cell at position cpos of Nc
+// along the line: K_g[a][a] / h plus, per face, the coefficient of u_a in the face terms of
+// sipg_line with the neighbour's line zero (interior face: sigma fv^2 - sign fv fd / h;
+// Dirichlet mirror: twice that; Neumann: nothing).
+template <int N>
+__device__ __forceinline__ double sipg_line_diag(const ct::DGTab<N, double> &tb, int a, int cpos, int Nc,
+                                                 double h, double sigma, int dmask) {
+  double v = tb.kgd[a] / h;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const bool has = s ? cpos < Nc - 1 : cpos > 0;
+    const double fvo = s ? tb.fv0[N - 1 - a] : tb.fv0[a];
+    const double fdo = s ? -tb.fd0[N - 1 - a] : tb.fd0[a];
+    const double sign = s ? 1.0 : -1.0;
+    const double term = sigma * fvo * fvo - sign * fvo * fdo / h;
+    if (has)
+      v += term;
+    else if ((dmask >> s) & 1)
+      v += 2.0 * term;
+  }
+  return v;
+}
+
+// diag(A): per DoF the sum over the three directions of the tangential weights h^2 w w times
+// the own-cell diagonal of that direction's line operator (the operator is a Kronecker sum).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+sipg_diag_kernel(double *__restrict__ d, int Nc, double h, double sigma, int dmask) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  constexpr const ct::DGTab<n, double> &tb = ct::DGTables<n, double>::tab;
+  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t cell = i / n3;
+    const int r = int(i - cell * n3), a = r % n, b = (r / n) % n, c = r / (n * n);
+    const int cx = int(cell % Nc), cy = int((cell / Nc) % Nc), cz = int(cell / (int64_t(Nc) * Nc));
+    d[i] = h * h * (tb.w[b] * tb.w[c] * sipg_line_diag<n>(tb, a, cx, Nc, h, sigma, dmask) +
+                    tb.w[a] * tb.w[c] * sipg_line_diag<n>(tb, b, cy, Nc, h, sigma, dmask) +
+                    tb.w[a] * tb.w[b] * sipg_line_diag<n>(tb, c, cz, Nc, h, sigma, dmask));
+  }
+}
+
+// Embedding of the coarse DG space in the fine one, one work-group per coarse cell:
+// xf(child) += (E_sz (x) E_sy (x) E_sx) xc(cell) for the 8 children (sx, sy, sz), where
+// E_s[f][c] = coarse basis c at the f-th Gauss point of child s.  Fine cells belong to
+// exactly one coarse cell, so no atomics.
+template <int K, typename TC, typename TF>
+__global__ void __launch_bounds__(kBlock)
+dg_prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, TransferTab tt) {
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n;
+  __shared__ double E[2 * n2];
+  __shared__ TF u[n3], t1[2 * n3], t2[4 * n3];
+  for (int i = threadIdx.x; i < 2 * n2; i += kBlock) E[i] = tt.E[i];
+  const int64_t cell = blockIdx.x;
+  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const int Nf = 2 * Ncc;
+  for (int i = threadIdx.x; i < n3; i += kBlock) u[i] = TF(xc[cell * n3 + i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * n3; i += kBlock) {   // x: [sx][c][b][a]
+    const int sx = i / n3, r = i - sx * n3, a = r % n, bc = r / n;
+    TF v = 0;
+    for (int j = 0; j < n; ++j) v += TF(E[(sx * n + a) * n + j]) * u[bc * n + j];
+    t1[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * n3; i += kBlock) {   // y: [sy][sx][c][b][a]
+    const int sy = i / (2 * n3), rest = i - sy * 2 * n3, sx = rest / n3, r = rest - sx * n3;
+    const int a = r % n, b = (r / n) % n, c = r / n2;
+    TF v = 0;
+    for (int j = 0; j < n; ++j) v += TF(E[(sy * n + b) * n + j]) * t1[sx * n3 + c * n2 + j * n + a];
+    t2[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 8 * n3; i += kBlock) {   // z: fine cell (sx, sy, sz)
+    const int sz = i / (4 * n3), rest = i - sz * 4 * n3, sy = rest / (2 * n3), rest2 = rest - sy * 2 * n3;
+    const int sx = rest2 / n3, r = rest2 - sx * n3, a = r % n, b = (r / n) % n, c = r / n2;
+    TF v = 0;
+    for (int j = 0; j < n; ++j) v += TF(E[(sz * n + c) * n + j]) * t2[(sy * 2 + sx) * n3 + j * n2 + b * n + a];
+    const int64_t fc = (2 * cx + sx) + int64_t(Nf) * ((2 * cy + sy) + int64_t(Nf) * (2 * cz + sz));
+    xf[fc * n3 + r] += v;
+  }
+}
+
+// coarse = P^T (b_f - A x_f) (axf == nullptr: P^T b_f), one work-group per coarse cell:
+// the transposed embedding of the 8 children summed; every coarse value is written once.
+template <int K, typename TF, typename TC>
+__global__ void __launch_bounds__(kBlock)
+dg_restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__restrict__ bc, int Ncc,
+                   TransferTab tt) {
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n;
+  __shared__ double E[2 * n2];
+  __shared__ TF r8[8 * n3], t2[4 * n3], t1[2 * n3];
+  for (int i = threadIdx.x; i < 2 * n2; i += kBlock) E[i] = tt.E[i];
+  const int64_t cell = blockIdx.x;
+  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const int Nf = 2 * Ncc;
+  for (int i = threadIdx.x; i < 8 * n3; i += kBlock) {   // children in order (sz, sy, sx)
+    const int ch = i / n3, r = i - ch * n3, sx = ch & 1, sy = (ch >> 1) & 1, sz = ch >> 2;
+    const int64_t fc = (2 * cx + sx) + int64_t(Nf) * ((2 * cy + sy) + int64_t(Nf) * (2 * cz + sz));
+    const int64_t g = fc * n3 + r;
+    r8[i] = axf ? bf[g] - axf[g] : bf[g];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * n3; i += kBlock) {   // z: [sy][sx][c'][b][a]
+    const int sy = i / (2 * n3), rest = i - sy * 2 * n3, sx = rest / n3, r = rest - sx * n3;
+    const int a = r % n, b = (r / n) % n, c = r / n2;
+    TF v = 0;
+    for (int sz = 0; sz < 2; ++sz)
+      for (int j = 0; j < n; ++j)
+        v += TF(E[(sz * n + j) * n + c]) * r8[(sz * 4 + sy * 2 + sx) * n3 + j * n2 + b * n + a];
+    t2[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * n3; i += kBlock) {   // y: [sx][c'][b'][a]
+    const int sx = i / n3, r = i - sx * n3, a = r % n, b = (r / n) % n, c = r / n2;
+    TF v = 0;
+    for (int sy = 0; sy < 2; ++sy)
+      for (int j = 0; j < n; ++j)
+        v += TF(E[(sy * n + j) * n + b]) * t2[(sy * 2 + sx) * n3 + c * n2 + j * n + a];
+    t1[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += kBlock) {       // x: coarse (a', b', c')
+    const int a = i % n, bc2 = i / n;
+    TF v = 0;
+    for (int sx = 0; sx < 2; ++sx)
+      for (int j = 0; j < n; ++j) v += TF(E[(sx * n + j) * n + a]) * t1[sx * n3 + bc2 * n + j];
+    bc[cell * n3 + i] = TC(v);
+  }
+}
+
+// Right-hand side of the three-Gaussian example for SIPG on [lo, lo + Nc h]^3, Gauss-point
+// basis: (f, psi_i) with the (k+1)^3 Gauss rule (= w w w h^3 f at the DoF's own point), plus
+// on each boundary face of the DoF's cell the data terms of the mirror extension (Sec. 2.2,
+// eq. bc_dgsip): Dirichlet int (2 sigma g psi_i - g n . grad psi_i), Neumann
+// int (n . grad u) psi_i, face Gauss points = the tangential Gauss points.
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+sipg_rhs_gaussians_kernel(double *__restrict__ b, int Nc, double h, double lo, double sigma, int dmask) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  constexpr const ct::DGTab<n, double> &tb = ct::DGTables<n, double>::tab;
+  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t cell = i / n3;
+    const int r = int(i - cell * n3);
+    const int idx[3] = {r % n, (r / n) % n, r / (n * n)};
+    const int cc[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
+    double x[3], u, g[3], lap;
+    for (int d = 0; d < 3; ++d) x[d] = lo + (cc[d] + tb.xg[idx[d]]) * h;
+    gaussians(x, u, g, lap);
+    double v = tb.w[idx[0]] * tb.w[idx[1]] * tb.w[idx[2]] * h * h * h * (-lap);
+    for (int d = 0; d < 3; ++d) {
+      const int a = idx[d];
+      const double W = tb.w[idx[(d + 1) % 3]] * tb.w[idx[(d + 2) % 3]] * h * h;
+      for (int s = 0; s < 2; ++s) {
+        if (cc[d] != (s ? Nc - 1 : 0)) continue;
+        const double fvo = s ? tb.fv0[n - 1 - a] : tb.fv0[a];
+        const double fdo = s ? -tb.fd0[n - 1 - a] : tb.fd0[a];
+        const double sign = s ? 1.0 : -1.0;
+        double xf[3] = {x[0], x[1], x[2]}, uf, gf[3], lf;
+        xf[d] = lo + (cc[d] + s) * h;
+        gaussians(xf, uf, gf, lf);
+        if ((dmask >> s) & 1)
+          v += W * (2.0 * sigma * uf * fvo - uf * sign * fdo / h);
+        else
+          v += W * sign * gf[d] * fvo;
+      }
+    }
+    b[i] = v;
+  }
+}
+
+inline int grid_for(int64_t items, int cap = 16384) {
+  int64_t g = (items + kBlock - 1) / kBlock;
+  return int(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
 }  // namespace
 
 hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
@@ -185,6 +362,75 @@ hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const 
 #undef CASE
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_sipg_diagonal(const Context &c, const Level &L, hipStream_t s) {
+  const double sigma = c.p.penalty_factor * (c.k + 1) * (c.k + 1) / L.h;
+  const int dm = dirichlet_mask(c.p);
+#define CASE(K) sipg_diag_kernel<K><<<grid_for(L.ndofs), kBlock, 0, s>>>(L.diag64, L.Nc, L.h, sigma, dm); break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_diag_invert(L, s);
+}
+
+template <int K>
+static hipError_t dg_prolongate_k(const Context &c, const Level &coarse, const void *xc, int cd, void *xf,
+                                  int fd, hipStream_t s) {
+  const int grid = int(coarse.ncells);
+  if (cd == MFL_F64 && fd == MFL_F64)
+    dg_prolongate_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)xc, (double *)xf, coarse.Nc, c.transfer);
+  else if (cd == MFL_F64 && fd == MFL_F32)
+    dg_prolongate_kernel<K, double, float><<<grid, kBlock, 0, s>>>((const double *)xc, (float *)xf, coarse.Nc, c.transfer);
+  else if (cd == MFL_F32 && fd == MFL_F32)
+    dg_prolongate_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)xc, (float *)xf, coarse.Nc, c.transfer);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_prolongate_add(const Context &c, const Level &coarse, const void *xc, int cd, void *xf,
+                                    int fd, hipStream_t s) {
+#define CASE(K) return dg_prolongate_k<K>(c, coarse, xc, cd, xf, fd, s)
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <int K>
+static hipError_t dg_restrict_k(const Context &c, const Level &coarse, const void *bf, const void *axf, int fd,
+                                void *bc, int cd, hipStream_t s) {
+  const int grid = int(coarse.ncells);
+  if (fd == MFL_F64 && cd == MFL_F64)
+    dg_restrict_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)bf, (const double *)axf, (double *)bc, coarse.Nc, c.transfer);
+  else if (fd == MFL_F32 && cd == MFL_F64)
+    dg_restrict_kernel<K, float, double><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (double *)bc, coarse.Nc, c.transfer);
+  else if (fd == MFL_F32 && cd == MFL_F32)
+    dg_restrict_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)bf, (const float *)axf, (float *)bc, coarse.Nc, c.transfer);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_restrict(const Context &c, const Level &coarse, const void *bf, const void *axf, int fd,
+                              void *bc, int cd, hipStream_t s) {
+#define CASE(K) return dg_restrict_k<K>(c, coarse, bf, axf, fd, bc, cd, s)
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sipg_rhs_gaussians(const Context &c, const Level &L, double *b, hipStream_t s) {
+  const double sigma = c.p.penalty_factor * (c.k + 1) * (c.k + 1) / L.h;
+  const int dm = dirichlet_mask(c.p);
+#define CASE(K)                                                                                   \
+  sipg_rhs_gaussians_kernel<K><<<grid_for(L.ndofs), kBlock, 0, s>>>(b, L.Nc, L.h, c.p.domain_lo,   \
+                                                                    sigma, dm);                    \
+  break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipGetLastError();
 }
 
 }  // namespace mfl

@@ -76,9 +76,12 @@ EO<N, T> make_eo(const double *A) {   // A row-major N x N (row length N)
 }
 
 // Embedding of the coarse GLL basis in the fine grid lines of one coarse cell:
-// P[f (k+1) + i] = coarse basis i at the f-th of the 2k+1 fine points.
+// P[f (k+1) + i] = coarse basis i at the f-th of the 2k+1 fine points.  DG (Lagrange in
+// the Gauss points): E[(s n + f) n + c] = coarse basis c at the f-th Gauss point of child
+// s (the child covers [s/2, (s+1)/2] of the coarse cell).
 struct TransferTab {
   double P[kMaxM * kMaxN];
+  double E[2 * kMaxN * kMaxN];
 };
 
 struct Level {
@@ -161,6 +164,15 @@ hipError_t launch_lift(const Context &c, const Level &L, double *b, const double
                        hipStream_t s);
 hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
                              hipStream_t s);
+// SIPG: matrix diagonal (FP64, then inverse and FP32 copies), embedding transfers between
+// level `coarse` and the next finer one, and the right-hand side of the three-Gaussian example
+hipError_t launch_sipg_diagonal(const Context &c, const Level &L, hipStream_t s);
+hipError_t launch_dg_prolongate_add(const Context &c, const Level &coarse, const void *xc, int c_dtype,
+                                    void *xf, int f_dtype, hipStream_t s);
+hipError_t launch_dg_restrict(const Context &c, const Level &coarse, const void *bf, const void *axf,
+                              int f_dtype, void *bc, int c_dtype, hipStream_t s);
+hipError_t launch_sipg_rhs_gaussians(const Context &c, const Level &L, double *b, hipStream_t s);
+hipError_t launch_diag_invert(const Level &L, hipStream_t s);
 
 // multigrid and vector kernels
 hipError_t launch_fill(void *dst, int dtype, int64_t n, double value, hipStream_t s);

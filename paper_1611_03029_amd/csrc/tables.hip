@@ -142,6 +142,11 @@ void build_tables(int k, Tab<kMaxN, double> &t, Tab<kMaxN, float> &t32, Transfer
     lagrange_eval(n, xl, xi, v, d);
     for (int i = 0; i < n; ++i) tt.P[f * n + i] = v[i];
   }
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < n; ++f) {
+      lagrange_eval(n, xq, 0.5 * (s + xq[f]), v, d);
+      for (int c = 0; c < n; ++c) tt.E[(s * n + f) * n + c] = v[c];
+    }
 }
 
 }  // namespace mfl

@@ -54,7 +54,7 @@ def test_workspace_scales_with_geometry_and_multigrid():
 @pytest.mark.parametrize("kw", [dict(degree=0), dict(degree=9), dict(cells_per_dim=0),
                                 dict(disc=2), dict(geometry=5), dict(bc=3), dict(bc=-1), dict(mg_precision=7),
                                 dict(disc=mfl.SIPG, geometry=mfl.CURVED),
-                                dict(disc=mfl.SIPG, build_mg=True),
+                                dict(disc=mfl.SIPG, build_mg=True, bc=mfl.NEUMANN),
                                 dict(cells_per_dim=12, build_mg=True, min_level_cells=2),
                                 dict(build_mg=True, bc=mfl.NEUMANN),
                                 dict(geometry=mfl.CURVED, curve_amp=0.5),

@@ -71,12 +71,9 @@ def test_rhs_gaussians_with_dirichlet_everywhere():
     assert rel_err(prob.rhs_gaussians(), ref) <= 1e-12
 
 
-def test_rhs_gaussians_rejects_curved_and_sipg():
+def test_rhs_gaussians_rejects_curved_meshes():
     with pytest.raises(mfl.MflError) as e:
         mfl.Problem(2, 4, geometry=mfl.CURVED).rhs_gaussians()
-    assert e.value.code == mfl._mfl.MFL_EUNSUPPORTED
-    with pytest.raises(mfl.MflError) as e:
-        mfl.Problem(2, 4, disc=mfl.SIPG, bc=mfl.MIXED, **DOMAIN).rhs_gaussians()
     assert e.value.code == mfl._mfl.MFL_EUNSUPPORTED
 
 
