@@ -67,6 +67,8 @@ extern "C" {
 #define MFL_BC_MIXED 2        /* Neumann at x_e = lo, Dirichlet at x_e = lo + len (Sec. 5) */
 #define MFL_F64 0
 #define MFL_F32 1
+#define MFL_DG_JACOBI_GAUSS 0  /* SIPG smoother: point Jacobi of the Gauss-point basis */
+#define MFL_DG_JACOBI_GLL 1    /* ... point Jacobi of the GLL-Lagrange basis of each cell */
 
 typedef struct mfl_params {
   int degree;             /* polynomial degree k, 1..8 */
@@ -86,6 +88,11 @@ typedef struct mfl_params {
   int build_mg;           /* 0: finest-level operator only; 1: multigrid hierarchy */
   double domain_lo;       /* the mesh covers [domain_lo, domain_lo + domain_len]^3 (0) */
   double domain_len;      /* (1; curved meshes need the unit cube) */
+  int dg_jacobi_basis;    /* SIPG multigrid: basis whose point Jacobi the Chebyshev smoother
+                             uses.  MFL_DG_JACOBI_GLL (default): the Lagrange basis in the
+                             Gauss-Lobatto points, applied to the Gauss-basis vectors as
+                             T D'^{-1} T^T per cell (T = change of basis, D' = the operator's
+                             diagonal in that basis); MFL_DG_JACOBI_GAUSS: diag(A)^{-1}. */
 } mfl_params;
 
 typedef struct mfl_context *mfl_handle;

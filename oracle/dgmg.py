@@ -10,6 +10,12 @@ the paper for DG-SIP as well as for continuous elements).
 * Smoother, eigenvalue estimate, coarse solver and outer CG: the same textbook routines
   as for the continuous discretization (mg.chebyshev, mg.lanczos_max_eig, mg.coarse_steps,
   mg.pcg).  The DG operator has no Dirichlet rows: every DoF is an unknown.
+* Jacobi basis: point Jacobi acts on the coefficients of a basis.  jacobi_basis='gauss'
+  uses the Lagrange basis in the Gauss points (the basis of the vectors); 'gll' uses the
+  Lagrange basis in the Gauss-Lobatto points of each cell, expressed in the Gauss basis as
+  C = T D'^{-1} T^T with T = S (x) S (x) S per cell (S[q][j] = GLL basis j at Gauss point
+  q: the change of coefficients from the GLL to the Gauss basis) and D' = diag(T^T A T),
+  the diagonal of the operator in the GLL basis.
 
 Test infrastructure only: used by the tests, never by the library.
 """
@@ -17,7 +23,16 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import mg, sipg
-from .basis import lagrange_values
+from .basis import gauss_lobatto, lagrange_values
+
+
+def gll_change_of_basis(dg):
+    """Block-diagonal T (per cell S (x) S (x) S) mapping GLL-basis coefficients to
+    Gauss-basis coefficients of the same polynomials."""
+    xl, _ = gauss_lobatto(dg.n)
+    S = lagrange_values(xl, dg.nodes)              # (Gauss points, GLL basis)
+    T3 = np.kron(S, np.kron(S, S))
+    return sp.block_diag([T3] * dg.n_cells).tocsr()
 
 
 def child_embedding_1d(dg_coarse):
@@ -56,7 +71,7 @@ class DGMultigrid:
 
     def __init__(self, fine_cells, degree, c_pen=1.0, bc="dirichlet", lo=0.0, length=1.0,
                  min_cells=2, cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15,
-                 coarse_eps=1e-3):
+                 coarse_eps=1e-3, jacobi_basis="gauss"):
         self.cheb_updates = cheb_degree + 1
         sizes = []
         Nc = fine_cells
@@ -70,11 +85,24 @@ class DGMultigrid:
         for l, Nc in enumerate(sizes):
             dg = sipg.DGBox(Nc, degree, c_pen=c_pen, lo=lo, length=length)
             A = sipg.assemble(dg, bc)
-            Dinv = 1.0 / A.diagonal()
+            if jacobi_basis == "gll":
+                T = gll_change_of_basis(dg)
+                dpinv = 1.0 / (T.T @ A @ T).diagonal()
+                Dinv = (lambda T, dpinv: lambda r: T @ (dpinv * (T.T @ r)))(T, dpinv)
+            elif jacobi_basis == "gauss":
+                Dinv = 1.0 / A.diagonal()
+            else:
+                raise ValueError(jacobi_basis)
             lev = {"box": dg, "A": A, "Dinv": Dinv}
             if l == 0:
-                di = np.sqrt(Dinv)
-                ev = np.linalg.eigvalsh(di[:, None] * A.toarray() * di[None, :])
+                # C (the Jacobi step as a matrix) is symmetric positive definite: the
+                # spectrum of C A is that of L^T A L with C = L L^T
+                if jacobi_basis == "gll":
+                    C = (T @ sp.diags(dpinv) @ T.T).toarray()
+                else:
+                    C = np.diag(Dinv)
+                Lc = np.linalg.cholesky(C)
+                ev = np.linalg.eigvalsh(Lc.T @ A.toarray() @ Lc)
                 lev["lmin"], lev["lmax"] = float(ev.min()), float(ev.max())
                 lev["steps"] = mg.coarse_steps(lev["lmin"], lev["lmax"], coarse_eps)
             else:
@@ -86,6 +114,10 @@ class DGMultigrid:
         self.fine_products = 0
 
     vcycle = mg.Multigrid.vcycle
+
+    def jacobi(self, l, r):
+        """The Jacobi step of level l applied to r."""
+        return mg.precondition(self.levels[l]["Dinv"], r)
 
 
 def solve(fine_cells, degree, b, c_pen=1.0, tol=1e-10, maxit=200, **mg_kwargs):

@@ -59,6 +59,12 @@ def prolongation(coarse, fine, bc="dirichlet"):
     return (keep_f @ P @ keep_c).tocsr()
 
 
+def precondition(Dinv, r):
+    """Jacobi step: Dinv * r for a vector of inverse diagonal entries, Dinv(r) when Dinv is
+    a callable (a smoother preconditioner other than the point Jacobi of the basis)."""
+    return Dinv(r) if callable(Dinv) else Dinv * r
+
+
 def lanczos_max_eig(A, Dinv, key, iters=15, bmask=None):
     """Largest Ritz value of `iters` Jacobi-preconditioned CG steps on A x = b,
     b = SplitMix64 stream `key` in [-1, 1) with Dirichlet entries zeroed."""
@@ -73,7 +79,7 @@ def cg_lanczos(A, Dinv, key, iters, bmask=None):
         b[bmask] = 0.0
     x = np.zeros(n)
     r = b.copy()
-    z = Dinv * r
+    z = precondition(Dinv, r)
     p = z.copy()
     rz = r @ z
     alphas, betas = [], []
@@ -82,14 +88,14 @@ def cg_lanczos(A, Dinv, key, iters, bmask=None):
         alpha = rz / (p @ q)
         x += alpha * p
         r -= alpha * q
-        z = Dinv * r
+        z = precondition(Dinv, r)
         rz_new = r @ z
         beta = rz_new / rz
         alphas.append(alpha)
         betas.append(beta)
         rz = rz_new
         p = z + beta * p
-        if rz_new <= 1e-30 * (b @ (Dinv * b)):
+        if rz_new <= 1e-30 * (b @ precondition(Dinv, b)):
             break
     m = len(alphas)
     T = np.zeros((m, m))
@@ -114,7 +120,7 @@ def chebyshev(A, Dinv, b, x0, lo, hi, updates):
         x = x0.copy()
         r = b - A @ x
         products += 1
-    d = Dinv * r / theta
+    d = precondition(Dinv, r) / theta
     if updates > 1:
         sigma1 = theta / delta
         rho = 1.0 / sigma1
@@ -123,7 +129,7 @@ def chebyshev(A, Dinv, b, x0, lo, hi, updates):
         r = b - A @ x
         products += 1
         rho_new = 1.0 / (2.0 * sigma1 - rho)
-        d = rho_new * rho * d + (2.0 * rho_new / delta) * (Dinv * r)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * precondition(Dinv, r)
         rho = rho_new
     x += d
     return x, products

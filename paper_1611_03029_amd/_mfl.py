@@ -15,6 +15,7 @@ MFL_OK, MFL_EINVAL, MFL_ENOCONV, MFL_EBREAKDOWN, MFL_EHIP, MFL_EUNSUPPORTED = 0,
 CG, SIPG = 0, 1
 CARTESIAN, CURVED = 0, 1
 DIRICHLET, NEUMANN, MIXED = 0, 1, 2
+DG_JACOBI_GAUSS, DG_JACOBI_GLL = 0, 1
 F64, F32 = 0, 1
 _DT = {F64: torch.float64, F32: torch.float32}
 
@@ -44,6 +45,7 @@ class Params(ctypes.Structure):
         ("build_mg", ctypes.c_int),
         ("domain_lo", ctypes.c_double),
         ("domain_len", ctypes.c_double),
+        ("dg_jacobi_basis", ctypes.c_int),
     ]
 
 
@@ -107,7 +109,7 @@ def _ptr(t):
 def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.1, bc=DIRICHLET,
                 penalty_factor=1.0, build_mg=False, mg_precision=F64, min_level_cells=2,
                 cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3,
-                domain_lo=0.0, domain_len=1.0):
+                domain_lo=0.0, domain_len=1.0, dg_jacobi_basis=DG_JACOBI_GLL):
     p = Params()
     _check(lib().mfl_default_params(ctypes.byref(p)))
     p.degree, p.cells_per_dim, p.min_level_cells = degree, cells_per_dim, min_level_cells
@@ -116,6 +118,7 @@ def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.
     p.cheb_degree, p.cheb_lo, p.cheb_hi = cheb_degree, cheb_lo, cheb_hi
     p.eig_iters, p.coarse_tol = eig_iters, coarse_tol
     p.domain_lo, p.domain_len = domain_lo, domain_len
+    p.dg_jacobi_basis = dg_jacobi_basis
     return p
 
 

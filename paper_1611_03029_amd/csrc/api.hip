@@ -48,6 +48,8 @@ int check_params(const mfl_params *p) {
     return fail(MFL_EINVAL, "unknown bc %d", p->bc);
   if (!(std::isfinite(p->domain_lo) && p->domain_len > 0.0 && std::isfinite(p->domain_len)))
     return fail(MFL_EINVAL, "need a finite domain_lo and 0 < domain_len < inf");
+  if (p->dg_jacobi_basis != MFL_DG_JACOBI_GAUSS && p->dg_jacobi_basis != MFL_DG_JACOBI_GLL)
+    return fail(MFL_EINVAL, "unknown dg_jacobi_basis %d", p->dg_jacobi_basis);
   if (p->mg_precision != MFL_F64 && p->mg_precision != MFL_F32)
     return fail(MFL_EINVAL, "unknown mg_precision %d", p->mg_precision);
   if (p->disc == MFL_DISC_SIPG) {
@@ -233,6 +235,17 @@ int read_scalars(Context &c, hipStream_t s) {
   return MFL_OK;
 }
 
+// SIPG multigrid smoothed with the point Jacobi of the GLL-Lagrange basis (see
+// launch_sipg_gll_jacobi_diag); otherwise point Jacobi of the vectors' own basis.
+bool gll_jacobi(const Context &c) {
+  return c.p.disc == MFL_DISC_SIPG && c.p.dg_jacobi_basis == MFL_DG_JACOBI_GLL;
+}
+
+hipError_t jacobi_step(const Context &c, const Level &L, const double *r, double *z, hipStream_t s) {
+  if (gll_jacobi(c)) return launch_dg_gll_jacobi(c, L, r, z, s);
+  return launch_jacobi(L.dinv64, r, z, L.ndofs, s);
+}
+
 // Faces whose DoFs are identity rows of the operator: the Dirichlet faces for CG; none for
 // SIPG, which imposes Dirichlet data weakly.
 int row_mask(const Context &c) { return c.p.disc == MFL_DISC_CG ? dirichlet_mask(c.p) : 0; }
@@ -245,7 +258,7 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
   const int64_t N = L.ndofs;
   double *r = c.r, *z = c.z, *p = c.pv, *q = c.q;
   HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), row_mask(c), s));
-  HIP_TRY(launch_jacobi(L.dinv64, r, z, N, s));
+  HIP_TRY(jacobi_step(c, L, r, z, s));
   HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
   HIP_TRY(launch_finalize(c.partials, c.scalars, kRZ, kFinSum, s));
@@ -259,7 +272,7 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
     HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s));
     // r -= alpha q (x is not needed: the z buffer takes the x update and is overwritten)
     HIP_TRY(launch_pcg_update_xr(z, r, p, q, c.scalars, N, c.partials, s));
-    HIP_TRY(launch_jacobi(L.dinv64, r, z, N, s));
+    HIP_TRY(jacobi_step(c, L, r, z, s));
     HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
     HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinBeta, s));
     HIP_TRY(launch_pcg_update_p(p, z, c.scalars, N, s));
@@ -289,7 +302,10 @@ int rebuild_kappa_dependent(Context &c, hipStream_t s) {
     if (c.p.disc == MFL_DISC_CG)
       HIP_TRY(launch_cg_diagonal(c, c.levels[l], s));
     else
+    {
       HIP_TRY(launch_sipg_diagonal(c, c.levels[l], s));
+      if (gll_jacobi(c)) HIP_TRY(launch_sipg_gll_jacobi_diag(c, c.levels[l], s));
+    }
   }
   if (!c.p.build_mg) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -326,6 +342,12 @@ int rebuild_kappa_dependent(Context &c, hipStream_t s) {
 int dtype_of(const Level &L) { return L.mg_f32 ? MFL_F32 : MFL_F64; }
 const void *dinv_of(const Level &L) { return L.mg_f32 ? (const void *)L.dinv32 : (const void *)L.dinv64; }
 
+// d = c1 d + c2 C (b - A x); x += d with the level's Jacobi step C.
+hipError_t cheb_step(const Context &c, Level &L, double *x64_out, int dt, double c1, double c2, hipStream_t s) {
+  if (gll_jacobi(c)) return launch_dg_gll_cheb_step(c, L, L.b, L.ax, L.d, L.x, x64_out, dt, c1, c2, s);
+  return launch_cheb_step(L.b, L.ax, dinv_of(L), L.d, L.x, x64_out, dt, L.ndofs, c1, c2, s);
+}
+
 // Chebyshev iteration on level l with interval [lo, hi] and `updates` updates of x.
 // zero_start: x = 0 initially and b is taken from b_in (stored into L.b when b_in != L.b).
 int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_start, const void *b_in,
@@ -338,21 +360,23 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
   int done = 0;
   const bool last_writes = x64_out != nullptr;
   if (zero_start) {
-    HIP_TRY(launch_cheb_first(b_in, b_dtype, b_in == L.b ? nullptr : L.b, dinv_of(L), L.d, L.x, dt, N,
-                              1.0 / theta, s));
+    if (gll_jacobi(c))
+      HIP_TRY(launch_dg_gll_cheb_first(c, L, b_in, b_dtype, b_in == L.b ? nullptr : L.b, L.d, L.x, dt,
+                                       1.0 / theta, s));
+    else
+      HIP_TRY(launch_cheb_first(b_in, b_dtype, b_in == L.b ? nullptr : L.b, dinv_of(L), L.d, L.x, dt, N,
+                                1.0 / theta, s));
     if (updates == 1 && last_writes) HIP_TRY(launch_cast(L.x, dt, x64_out, MFL_F64, N, s));
   } else {
     if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
-    HIP_TRY(launch_cheb_step(L.b, L.ax, dinv_of(L), L.d, L.x, (updates == 1) ? x64_out : nullptr, dt,
-                             N, 0.0, 1.0 / theta, s));
+    HIP_TRY(cheb_step(c, L, (updates == 1) ? x64_out : nullptr, dt, 0.0, 1.0 / theta, s));
   }
   done = 1;
   double rho = delta > 0.0 ? delta / theta : 0.0;   // 1 / sigma_1
   for (; done < updates; ++done) {
     const double rho_new = 1.0 / (2.0 * theta / delta - rho);
     if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
-    HIP_TRY(launch_cheb_step(L.b, L.ax, dinv_of(L), L.d, L.x, done + 1 == updates ? x64_out : nullptr,
-                             dt, N, rho_new * rho, 2.0 * rho_new / delta, s));
+    HIP_TRY(cheb_step(c, L, done + 1 == updates ? x64_out : nullptr, dt, rho_new * rho, 2.0 * rho_new / delta, s));
     rho = rho_new;
   }
   return MFL_OK;
@@ -465,6 +489,7 @@ int mfl_default_params(mfl_params *p) {
   p->build_mg = 0;
   p->domain_lo = 0.0;
   p->domain_len = 1.0;
+  p->dg_jacobi_basis = MFL_DG_JACOBI_GLL;
   return MFL_OK;
 }
 

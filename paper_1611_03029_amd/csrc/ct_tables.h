@@ -205,5 +205,32 @@ struct DGTables {
   static constexpr DGTab<N, T> tab = dgtab<N, T>();
 };
 
+// For the Jacobi smoother of the GLL-Lagrange basis on DG cells: the diagonals of the GLL
+// mass and stiffness matrices (k+1 Gauss quadrature, reference [0,1]) and the derivative of
+// the first GLL Lagrange polynomial at 0 (by symmetry the last one has -d0 at 1).
+template <int N, typename T>
+struct GLLDiag {
+  T m[N], k[N];
+  T d0;
+};
+
+template <int N, typename T>
+constexpr GLLDiag<N, T> glldiag() {
+  const Dense<N> d = dense<N>();
+  const Rules<N> r = rules<N>();
+  GLLDiag<N, T> g{};
+  for (int i = 0; i < N; ++i) {
+    g.m[i] = T(d.M[i * N + i]);
+    g.k[i] = T(d.K[i * N + i]);
+  }
+  g.d0 = T(lagrange<N>(r.xl, 0, 0.0).dP);
+  return g;
+}
+
+template <int N, typename T>
+struct GLLDiagTables {
+  static constexpr GLLDiag<N, T> tab = glldiag<N, T>();
+};
+
 }  // namespace ct
 }  // namespace mfl

@@ -343,6 +343,142 @@ sipg_rhs_gaussians_kernel(double *__restrict__ b, int Nc, double h, double lo, d
   }
 }
 
+// D'^{-1}, D' = diagonal of the SIPG operator in the GLL-Lagrange basis of each cell.  With
+// T = S (x) S (x) S the operator there is sum_d (h M) (x) (h M) (x) S^T A1_d S, whose line
+// part has the own-cell diagonal K[a][a] / h plus, for the end node a of a face (GLL nodes
+// lie on the faces), f (sigma + d0 / h) with f = 1 (interior), 2 (Dirichlet), 0 (Neumann).
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+sipg_gll_jacobi_diag_kernel(double *__restrict__ i64, float *__restrict__ i32, int Nc, double h,
+                            double sigma, int dmask) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  constexpr const ct::GLLDiag<n, double> &g = ct::GLLDiagTables<n, double>::tab;
+  const int64_t total = int64_t(Nc) * Nc * Nc * n3;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t cell = i / n3;
+    const int r = int(i - cell * n3);
+    const int idx[3] = {r % n, (r / n) % n, r / (n * n)};
+    const int cc[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
+    double line[3];
+    for (int d = 0; d < 3; ++d) {
+      const int a = idx[d];
+      double v = g.k[a] / h;
+      for (int s = 0; s < 2; ++s) {
+        if (a != (s ? K : 0)) continue;
+        const bool has = s ? cc[d] < Nc - 1 : cc[d] > 0;
+        const double f = has ? 1.0 : (((dmask >> s) & 1) ? 2.0 : 0.0);
+        v += f * (sigma + g.d0 / h);
+      }
+      line[d] = v;
+    }
+    const double dv = h * h * (g.m[idx[1]] * g.m[idx[2]] * line[0] + g.m[idx[0]] * g.m[idx[2]] * line[1] +
+                               g.m[idx[0]] * g.m[idx[1]] * line[2]);
+    i64[i] = 1.0 / dv;
+    i32[i] = float(1.0 / dv);
+  }
+}
+
+// Jacobi step of the GLL-Lagrange basis applied to Gauss-basis vectors, per cell
+// C w = T (D'^{-1} (T^T w)), fused with the smoother updates:
+//   MODE 0 (first Chebyshev update): w = b_in; d = C w * c1; x = d; b_store = b_in if given
+//   MODE 1 (Chebyshev update):      w = b - ax; d = c1 d + c2 C w; x += d; x64 = x if given
+//   MODE 2 (Jacobi step):           d = C w, w = b_in
+// n^2 lanes per cell, one line each; five phases with LDS transposes: S^T along z, y, x;
+// D'^{-1}; S along x, y, z.  The lane's z-line of w is read and its z-line of the result
+// written, so global accesses of consecutive lanes are contiguous within a cell.
+template <int K, typename A, typename T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const T *__restrict__ ax,
+                     const T *__restrict__ dpinv, T *__restrict__ d, T *__restrict__ x,
+                     double *__restrict__ x64, int64_t ncells, T c1, T c2) {
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = kBlock / n2;
+  constexpr const EOTab<n, T> &eo = ct::Tables<n, T>::eo;
+  __shared__ T U[CPB * n3], V[CPB * n3];
+  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2, i0 = p % n, i1 = p / n;
+  const int64_t cell = int64_t(xcd_block(blockIdx.x, gridDim.x)) * CPB + lc;
+  const bool inblk = lc < CPB;
+  const bool active = inblk && cell < ncells;
+  const int slot = inblk ? lc : 0;
+  T *Uc = U + slot * n3, *Vc = V + slot * n3;
+  const int64_t base = (active ? cell : 0) * n3;
+  // phase 1: z-lines (x = i0, y = i1): w, S^T along z
+  if (inblk) {
+    T w[n], r[n];
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      const int64_t gi = base + l * n2 + p;
+      T v = 0;
+      if (active) {
+        v = T(b_in[gi]);
+        if (MODE == 0 && b_store) b_store[gi] = v;
+        if (MODE == 1) v -= ax[gi];
+      }
+      w[l] = v;
+    }
+    eo_apply_t<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int l = 0; l < n; ++l) Uc[l * n2 + p] = r[l];
+  }
+  __syncthreads();
+  // phase 2: y-lines (x = i0, z = i1): S^T along y
+  if (inblk) {
+    T w[n], r[n];
+#pragma unroll
+    for (int b = 0; b < n; ++b) w[b] = Uc[i1 * n2 + b * n + i0];
+    eo_apply_t<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int b = 0; b < n; ++b) Vc[i1 * n2 + b * n + i0] = r[b];
+  }
+  __syncthreads();
+  // phase 3: x-lines (y = i0, z = i1): S^T along x, D'^{-1}, S along x
+  if (inblk) {
+    T w[n], r[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) w[a] = Vc[i1 * n2 + i0 * n + a];
+    eo_apply_t<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int a = 0; a < n; ++a) r[a] *= active ? dpinv[base + i1 * n2 + i0 * n + a] : T(0);
+    eo_apply<n, 1>(eo.S, r, w);
+#pragma unroll
+    for (int a = 0; a < n; ++a) Uc[i1 * n2 + i0 * n + a] = w[a];
+  }
+  __syncthreads();
+  // phase 4: y-lines: S along y
+  if (inblk) {
+    T w[n], r[n];
+#pragma unroll
+    for (int b = 0; b < n; ++b) w[b] = Uc[i1 * n2 + b * n + i0];
+    eo_apply<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int b = 0; b < n; ++b) Vc[i1 * n2 + b * n + i0] = r[b];
+  }
+  __syncthreads();
+  // phase 5: z-lines: S along z, then the update of the lane's z-line
+  if (active) {
+    T w[n], cw[n];
+#pragma unroll
+    for (int l = 0; l < n; ++l) w[l] = Vc[l * n2 + p];
+    eo_apply<n, 1>(eo.S, w, cw);
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      const int64_t gi = base + l * n2 + p;
+      if (MODE == 0) {
+        const T v = cw[l] * c1;
+        d[gi] = v;
+        x[gi] = v;
+      } else if (MODE == 1) {
+        const T dn = c1 * d[gi] + c2 * cw[l];
+        const T xn = x[gi] + dn;
+        d[gi] = dn;
+        x[gi] = xn;
+        if (x64) x64[gi] = double(xn);
+      } else {
+        d[gi] = cw[l];
+      }
+    }
+  }
+}
+
 inline int grid_for(int64_t items, int cap = 16384) {
   int64_t g = (items + kBlock - 1) / kBlock;
   return int(g < 1 ? 1 : (g > cap ? cap : g));
@@ -416,6 +552,69 @@ static hipError_t dg_restrict_k(const Context &c, const Level &coarse, const voi
 hipError_t launch_dg_restrict(const Context &c, const Level &coarse, const void *bf, const void *axf, int fd,
                               void *bc, int cd, hipStream_t s) {
 #define CASE(K) return dg_restrict_k<K>(c, coarse, bf, axf, fd, bc, cd, s)
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sipg_gll_jacobi_diag(const Context &c, const Level &L, hipStream_t s) {
+  const double sigma = c.p.penalty_factor * (c.k + 1) * (c.k + 1) / L.h;
+  const int dm = dirichlet_mask(c.p);
+#define CASE(K)                                                                                  \
+  sipg_gll_jacobi_diag_kernel<K><<<grid_for(L.ndofs), kBlock, 0, s>>>(L.dinv64, L.dinv32, L.Nc, L.h, \
+                                                                      sigma, dm);                  \
+  break
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipGetLastError();
+}
+
+template <int K, typename A, typename T, int MODE>
+static hipError_t dg_gll_k(const Level &L, const void *b_in, void *b_store, const void *ax, const void *dpinv,
+                           void *d, void *x, double *x64, double c1, double c2, hipStream_t s) {
+  constexpr int CPB = kBlock / ((K + 1) * (K + 1));
+  const int grid = int((L.ncells + CPB - 1) / CPB);
+  dg_gll_jacobi_kernel<K, A, T, MODE><<<grid, kBlock, 0, s>>>(
+      (const A *)b_in, (T *)b_store, (const T *)ax, (const T *)dpinv, (T *)d, (T *)x, x64, L.ncells, T(c1), T(c2));
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_gll_cheb_first(const Context &c, const Level &L, const void *b_in, int in_dtype,
+                                    void *b_store, void *d, void *x, int dtype, double inv_theta,
+                                    hipStream_t s) {
+  if (dtype == MFL_F64) {
+    if (in_dtype != MFL_F64) return hipErrorInvalidValue;
+#define CASE(K) return dg_gll_k<K, double, double, 0>(L, b_in, b_store, nullptr, L.dinv64, d, x, nullptr, inv_theta, 0.0, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else if (in_dtype == MFL_F64) {
+#define CASE(K) return dg_gll_k<K, double, float, 0>(L, b_in, b_store, nullptr, L.dinv32, d, x, nullptr, inv_theta, 0.0, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else {
+#define CASE(K) return dg_gll_k<K, float, float, 0>(L, b_in, b_store, nullptr, L.dinv32, d, x, nullptr, inv_theta, 0.0, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dg_gll_cheb_step(const Context &c, const Level &L, const void *b, const void *ax, void *d,
+                                   void *x, double *x64_out, int dtype, double c1, double c2, hipStream_t s) {
+  if (dtype == MFL_F64) {
+#define CASE(K) return dg_gll_k<K, double, double, 1>(L, b, nullptr, ax, L.dinv64, d, x, x64_out, c1, c2, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else {
+#define CASE(K) return dg_gll_k<K, float, float, 1>(L, b, nullptr, ax, L.dinv32, d, x, x64_out, c1, c2, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dg_gll_jacobi(const Context &c, const Level &L, const double *r, double *z, hipStream_t s) {
+#define CASE(K) return dg_gll_k<K, double, double, 2>(L, r, nullptr, nullptr, L.dinv64, z, nullptr, nullptr, 0.0, 0.0, s)
   MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   return hipErrorInvalidValue;

@@ -172,6 +172,17 @@ hipError_t launch_dg_prolongate_add(const Context &c, const Level &coarse, const
 hipError_t launch_dg_restrict(const Context &c, const Level &coarse, const void *bf, const void *axf,
                               int f_dtype, void *bc, int c_dtype, hipStream_t s);
 hipError_t launch_sipg_rhs_gaussians(const Context &c, const Level &L, double *b, hipStream_t s);
+// SIPG smoother with the point Jacobi of the GLL basis: L.dinv64 / L.dinv32 receive D'^{-1}
+// (cell-major, GLL index order) with D' = diag(T^T A T), T = S (x) S (x) S per cell
+hipError_t launch_sipg_gll_jacobi_diag(const Context &c, const Level &L, hipStream_t s);
+// the Chebyshev updates (cheb_first / cheb_step semantics) and the plain Jacobi step
+// z = C r with C = T D'^{-1} T^T instead of the point Jacobi of the Gauss basis
+hipError_t launch_dg_gll_cheb_first(const Context &c, const Level &L, const void *b_in, int in_dtype,
+                                    void *b_store, void *d, void *x, int dtype, double inv_theta,
+                                    hipStream_t s);
+hipError_t launch_dg_gll_cheb_step(const Context &c, const Level &L, const void *b, const void *ax, void *d,
+                                   void *x, double *x64_out, int dtype, double c1, double c2, hipStream_t s);
+hipError_t launch_dg_gll_jacobi(const Context &c, const Level &L, const double *r, double *z, hipStream_t s);
 hipError_t launch_diag_invert(const Level &L, hipStream_t s);
 
 // multigrid and vector kernels

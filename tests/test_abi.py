@@ -60,6 +60,7 @@ def test_workspace_scales_with_geometry_and_multigrid():
                                 dict(geometry=mfl.CURVED, curve_amp=0.5),
                                 dict(build_mg=True, cheb_lo=1.5),
                                 dict(domain_len=0.0), dict(domain_len=-2.0),
+                                dict(dg_jacobi_basis=2),
                                 dict(domain_lo=float("nan")),
                                 dict(geometry=mfl.CURVED, domain_lo=-1.0, domain_len=2.0)])
 def test_invalid_params_rejected(kw):
