@@ -12,7 +12,8 @@ Also reported, outside the timed region:
                 was taken on the current kernel source;
   fp32_apply    the same operator in FP32 (FP32 vectors and geometry factors);
   small_q2      CG Q2 on 8^3 cells: apply latency and the FP64 GMG-PCG solve;
-  sipg          SIPG Q3 and Q5 on 32^3 cells (FP64 apply);
+  sipg          SIPG Q3 and Q5 on 32^3 cells and, for steady state, 64^3 cells (FP64 apply),
+                with HBM and FP64-ALU fractions;
   paper_example time to solution of the paper's smooth-solution example (CG and DG-SIP),
                 next to the paper's own timings
   gmg_pcg       GMG-PCG time to solution, V-cycle in FP32 and in FP64 inside the FP64 outer
@@ -117,22 +118,34 @@ def small_config(steps):
             "pcg_fp64_mg_s": best, "iterations": its, "final_rel_residual": res}
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
 def sipg_configs(steps):
+    """SIPG Q3 and Q5 applies on 32^3 cells (the workload) and on 64^3 cells (steady state).
+    Fractions of both bounds: HBM with 16 B/DoF (src read and dst written once), FP64 ALU
+    with the element-centric flop model 2 (6 n^4 + 45 n^3) per cell (n = k+1)."""
     import torch
     import paper_1611_03029_amd as mfl
     from seeded_inputs import SEED_SIPG_Q3, SEED_SIPG_Q5, uniform_vector
     out = {}
-    for k, seed in ((3, SEED_SIPG_Q3), (5, SEED_SIPG_Q5)):
-        prob = mfl.Problem(k, 32, disc=mfl.SIPG)
-        u = torch.tensor(uniform_vector(prob.n_dofs, seed), device="cuda")
-        y = torch.empty_like(u)
-        ms, kms, _ = time_applies(prob, u, y, steps, 10)
-        byts = 16 * prob.n_dofs
-        out["Q%d_32^3" % k] = {"n_dofs": prob.n_dofs, "ms_per_apply": ms, "kernel_ms": kms,
-                               "dofs_per_s": prob.n_dofs / (ms * 1e-3),
-                               "equiv_dofs_per_s": prob.n_cells * k ** 3 / (ms * 1e-3),
-                               "hbm_frac_16B_per_dof": byts / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        del prob
+    for nc in (32, 64):
+        for k, seed in ((3, SEED_SIPG_Q3), (5, SEED_SIPG_Q5)):
+            prob = mfl.Problem(k, nc, disc=mfl.SIPG)
+            u = torch.tensor(uniform_vector(prob.n_dofs, seed), device="cuda")
+            y = torch.empty_like(u)
+            ms, kms, _ = time_applies(prob, u, y, steps if nc == 32 else max(steps // 4, 10), 10)
+            n = k + 1
+            byts = 16 * prob.n_dofs
+            flops = 2.0 * (6 * n ** 4 + 45 * n ** 3) * prob.n_cells
+            out["Q%d_%d^3" % (k, nc)] = {
+                "n_dofs": prob.n_dofs, "ms_per_apply": ms, "kernel_ms": kms,
+                "dofs_per_s": prob.n_dofs / (ms * 1e-3),
+                "equiv_dofs_per_s": prob.n_cells * k ** 3 / (ms * 1e-3),
+                "hbm_frac_16B_per_dof": byts / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "fp64_alu_frac": flops / (kms * 1e-3) / (FP64_VECTOR_PEAK_TFLOPS * 1e12)}
+            del prob, u, y
+            torch.cuda.empty_cache()
     return out
 
 
@@ -184,9 +197,11 @@ def paper_example(repeats=2):
         rec = {"cells": nc ** 3}
         for disc, name in ((mfl.CG, "cg"), (mfl.SIPG, "dg_sip")):
             for prec, pname in ((mfl.F32, "fp32_mg"), (mfl.F64, "fp64_mg")):
+                # the paper's hierarchy: uniform refinement of the coarse mesh, i.e. down to
+                # one cell for 2^m cells per direction and to 3^3 cells for 48^3
                 prob = mfl.Problem(k, nc, disc=disc, bc=mfl.MIXED, build_mg=True, mg_precision=prec,
                                    penalty_factor=3.0, domain_lo=-1.0, domain_len=2.0,
-                                   min_level_cells=3 if nc % 3 == 0 else 2)
+                                   min_level_cells=3 if nc % 3 == 0 else 1)
                 b = prob.rhs_gaussians()
                 best = None
                 for _ in range(repeats):

@@ -93,6 +93,9 @@ typedef struct mfl_params {
                              Gauss-Lobatto points, applied to the Gauss-basis vectors as
                              T D'^{-1} T^T per cell (T = change of basis, D' = the operator's
                              diagonal in that basis); MFL_DG_JACOBI_GAUSS: diag(A)^{-1}. */
+  int use_graphs;         /* 1 (default): the V-cycle is captured once as a HIP graph on an
+                             internal stream and replayed on the caller's stream; 0: kernel
+                             by kernel */
 } mfl_params;
 
 typedef struct mfl_context *mfl_handle;

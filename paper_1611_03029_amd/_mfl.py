@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("domain_lo", ctypes.c_double),
         ("domain_len", ctypes.c_double),
         ("dg_jacobi_basis", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
     ]
 
 
@@ -109,7 +110,7 @@ def _ptr(t):
 def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.1, bc=DIRICHLET,
                 penalty_factor=1.0, build_mg=False, mg_precision=F64, min_level_cells=2,
                 cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3,
-                domain_lo=0.0, domain_len=1.0, dg_jacobi_basis=DG_JACOBI_GLL):
+                domain_lo=0.0, domain_len=1.0, dg_jacobi_basis=DG_JACOBI_GLL, use_graphs=True):
     p = Params()
     _check(lib().mfl_default_params(ctypes.byref(p)))
     p.degree, p.cells_per_dim, p.min_level_cells = degree, cells_per_dim, min_level_cells
@@ -119,6 +120,7 @@ def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.
     p.eig_iters, p.coarse_tol = eig_iters, coarse_tol
     p.domain_lo, p.domain_len = domain_lo, domain_len
     p.dg_jacobi_basis = dg_jacobi_basis
+    p.use_graphs = int(bool(use_graphs))
     return p
 
 

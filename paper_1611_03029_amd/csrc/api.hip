@@ -294,8 +294,19 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
   return MFL_OK;
 }
 
+int drop_vcycle_graph(Context &c) {
+  if (c.vcycle_graph) {
+    HIP_TRY(hipGraphExecDestroy(c.vcycle_graph));
+    c.vcycle_graph = nullptr;
+  }
+  return MFL_OK;
+}
+
 // Everything that depends on kappa: coarse kappa, diagonals, eigenvalue estimates.
 int rebuild_kappa_dependent(Context &c, hipStream_t s) {
+  // the captured V-cycle holds the old smoother and coarse-solver coefficients
+  HIP_TRY(hipStreamSynchronize(s));
+  if (int rc = drop_vcycle_graph(c)) return rc;
   const int nl = int(c.levels.size());
   for (int l = nl - 2; l >= 0; --l) HIP_TRY(launch_coarsen_kappa(c.levels[l], c.levels[l + 1], s));
   for (int l = 0; l < nl; ++l) {
@@ -413,9 +424,43 @@ int cycle(Context &c, int l, const void *b_in, int b_dtype, double *x64_out, hip
   return chebyshev(c, l, lo, hi, updates, false, nullptr, dt, x64_out, s);
 }
 
+// Records one V-cycle c.r -> c.z on the internal capture stream (the caller's stream may
+// be the legacy default stream, which cannot be captured) and instantiates it.
+int capture_vcycle(Context &c) {
+  if (!c.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+  const int top = int(c.levels.size()) - 1;
+  HIP_TRY(hipStreamBeginCapture(c.capture_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = cycle(c, top, c.r, MFL_F64, c.z, c.capture_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c.capture_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(MFL_EHIP, "capture of the V-cycle: %s", hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&c.vcycle_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c.vcycle_graph = nullptr;
+    return fail(MFL_EHIP, "instantiation of the V-cycle graph: %s", hipGetErrorString(ei));
+  }
+  return MFL_OK;
+}
+
+// z = V-cycle(r).  With use_graphs the cycle on the work vectors runs as one graph launch
+// (other vectors are staged through r and z); otherwise kernel by kernel.
 int vcycle(Context &c, const double *r, double *z, hipStream_t s) {
   const int top = int(c.levels.size()) - 1;
-  return cycle(c, top, r, MFL_F64, z, s);
+  if (!c.p.use_graphs) return cycle(c, top, r, MFL_F64, z, s);
+  const int64_t N = c.levels.back().ndofs;
+  if (r != c.r) HIP_TRY(hipMemcpyAsync(c.r, r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!c.vcycle_graph) {
+    int rc = capture_vcycle(c);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipGraphLaunch(c.vcycle_graph, s));
+  if (z != c.z) HIP_TRY(hipMemcpyAsync(z, c.z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return MFL_OK;
 }
 
 int pcg(Context &c, const double *b, double *x, double rtol, int maxit, int *iters, double *res,
@@ -490,6 +535,7 @@ int mfl_default_params(mfl_params *p) {
   p->domain_lo = 0.0;
   p->domain_len = 1.0;
   p->dg_jacobi_basis = MFL_DG_JACOBI_GLL;
+  p->use_graphs = 1;
   return MFL_OK;
 }
 
@@ -725,6 +771,8 @@ int mfl_kappa_gradient(mfl_handle h, const double *u, const double *lambda, doub
 
 int mfl_destroy(mfl_handle h) {
   if (!h) return fail(MFL_EINVAL, "handle is NULL");
+  if (h->vcycle_graph) (void)hipGraphExecDestroy(h->vcycle_graph);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   if (h->host_scalars) (void)hipHostFree(h->host_scalars);
   for (hipEvent_t e : h->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->prof_stop) (void)hipEventDestroy(e);

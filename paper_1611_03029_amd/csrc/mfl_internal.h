@@ -119,6 +119,11 @@ struct Context {
   double *partials = nullptr;   // kReduceBlocks doubles
   double *scalars = nullptr;    // device scalars (see enum Scalar)
   double *host_scalars = nullptr;   // pinned host mirror
+  // the V-cycle on the work vectors r -> z, captured once as a HIP graph on an internal
+  // stream and replayed on the caller's stream (use_graphs); rebuilt when the smoother or
+  // coarse-solver parameters change
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t vcycle_graph = nullptr;
   // optional timing of the operator cell kernels of mfl_apply (HIP event pairs)
   bool profiling = false;
   int prof_used = 0;
