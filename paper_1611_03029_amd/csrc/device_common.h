@@ -57,6 +57,28 @@ __device__ __forceinline__ void cell_sync() {
     __syncthreads();
 }
 
+// Lane -> (cell slot, lane within the cell) of a work-group.  WAVE: every cell's N2 lanes
+// lie inside one wavefront (64 / N2 cells per wavefront); otherwise cells are packed densely
+// over the work-group and may straddle wavefronts.
+template <int N2, bool WAVE>
+struct LaneMap {
+  int slot, p;
+  bool used;   // lane belongs to a cell slot below `slots`
+  __device__ __forceinline__ LaneMap(int t, int slots) {
+    if constexpr (WAVE) {
+      constexpr int CPW = 64 / N2;
+      const int w = t / 64, ln = t % 64, s = ln / N2;
+      slot = w * CPW + s;
+      p = ln - s * N2;
+      used = s < CPW && slot < slots;
+    } else {
+      slot = t / N2;
+      p = t - slot * N2;
+      used = slot < slots;
+    }
+  }
+};
+
 // Copy of the first N*N entries of the kMaxN-sized host tables (rows of length N).
 template <int N, typename T>
 Tab<N, T> shrink_tab(const Tab<kMaxN, T> &t) {

@@ -50,26 +50,6 @@ template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks =
 template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; static constexpr bool wave = true; };
 template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2; static constexpr bool wave = false; };
 
-// Lane -> (cell slot, lane within the cell) of a work-group of kBlock lanes.
-template <int N2, bool WAVE>
-struct LaneMap {
-  int slot, p;
-  bool used;   // lane belongs to a cell slot below `slots`
-  __device__ __forceinline__ LaneMap(int t, int slots) {
-    if constexpr (WAVE) {
-      constexpr int CPW = 64 / N2;
-      const int w = t / 64, ln = t % 64, s = ln / N2;
-      slot = w * CPW + s;
-      p = ln - s * N2;
-      used = s < CPW && slot < slots;
-    } else {
-      slot = t / N2;
-      p = t - slot * N2;
-      used = slot < slots;
-    }
-  }
-};
-
 struct CellCtx {
   int i0, i1;        // lane coordinates within the cell
   int cz;            // cell coordinate in z (x, y enter through gx, gy)
@@ -111,14 +91,26 @@ __device__ __forceinline__ void gather_zline(const CellCtx &cc, const T *__restr
   for (int l = 0; l < N; ++l) u[l] = (cc.active && !z_bnd(cc, l)) ? src[cc.base + cc.plane * l] : T(0);
 }
 
-// The metric of the lane's z-line of Gauss points (layout [6][q] per cell).
-template <int N, typename T>
+// The metric of the lane's z-line of Gauss points (layout [6][q] per cell).  The metric is
+// streamed once per application; with NT the loads are non-temporal so that they do not
+// displace the src lines that neighbouring bricks re-read from L2 (measured: 4-10% faster
+// for the FP64 kernels up to k = 4, slower for FP32 and higher degrees).
+template <int N, bool NT, typename T>
 __device__ __forceinline__ void load_metric(bool active, const T *__restrict__ gm, int p, T (&g)[6][N]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c)
 #pragma unroll
-    for (int l = 0; l < N; ++l) g[c][l] = active ? gm[c * N * N * N + l * N * N + p] : T(0);
+    for (int l = 0; l < N; ++l) {
+      const T *a = gm + c * N * N * N + l * N * N + p;
+      if constexpr (NT)
+        g[c][l] = active ? __builtin_nontemporal_load(a) : T(0);
+      else
+        g[c][l] = active ? *a : T(0);
+    }
 }
+
+template <int K, typename T>
+constexpr bool kStreamMetric = sizeof(T) == 8 && K <= 4;
 
 struct NoOp {
   __device__ void operator()() const {}
@@ -410,7 +402,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   T u[n];
   T g[6][CURVED ? n : 1];
   gather_zline(cc, src, u);
-  if constexpr (CURVED) load_metric(cc.active, metric + cell * (6 * n3), p, g);
+  if constexpr (CURVED) load_metric<n, kStreamMetric<K, T>>(cc.active, metric + cell * (6 * n3), p, g);
   T kap = cc.active ? kappa[cell] : T(0);
 
 #pragma unroll
@@ -424,7 +416,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
       curved_cell<K, T, TX, TY, WL>(
           cc, u, g, kap, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
           [&] {
-            load_metric(cn.active, metric + celln * (6 * n3), p, g);
+            load_metric<n, kStreamMetric<K, T>>(cn.active, metric + celln * (6 * n3), p, g);
             kap = cn.active ? kappa[celln] : T(0);
           });
     } else {
@@ -598,7 +590,7 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
   gather_zline(cc, u, ul);
   if constexpr (CURVED) {
     T g[6][n];
-    load_metric(active, metric + (active ? cell : 0) * (6 * n3), p, g);
+    load_metric<n, false>(active, metric + (active ? cell : 0) * (6 * n3), p, g);
     curved_cell<K, T>(cc, ul, g, T(1), A, B, C, eo);
   } else {
     T *D = sm[NBUF - 1] + slot * n3;

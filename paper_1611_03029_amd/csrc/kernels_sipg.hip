@@ -24,6 +24,16 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Lane layout of the cell kernels: cells inside one wavefront (phases without work-group
+// barriers) where that fills the wavefront (k <= 3: 64, 63 and 64 lanes); denser packing
+// over the work-group otherwise (measured faster for k = 4 and 6).
+template <int K>
+struct DGLanes {
+  static constexpr int n2 = (K + 1) * (K + 1);
+  static constexpr bool wave = K <= 3;
+  static constexpr int cpb = wave ? (kBlock / 64) * (64 / n2) : kBlock / n2;   // cells per block
+};
+
 // t = scale * A1-part of one line: cell term K_g u / h plus the two faces of the cell along
 // this direction (face 0 at xi = 0 with outward normal -1, face 1 at xi = 1 with +1).
 // uL / uR: the neighbour cells' lines (used when hasL / hasR); without a neighbour the face
@@ -83,14 +93,16 @@ __device__ __forceinline__ void sipg_line(const ct::DGTab<N, T> &tb, const T *u,
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
 sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma, int dmask) {
-  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = kBlock / n2;
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = DGLanes<K>::cpb;
+  constexpr bool WL = DGLanes<K>::wave;
   constexpr const ct::DGTab<n, T> &tb = ct::DGTables<n, T>::tab;
   __shared__ T U[CPB * n3], R[CPB * n3];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2, i0 = p % n, i1 = p / n;
+  const LaneMap<n2, WL> lm(threadIdx.x, CPB);
+  const int lc = lm.slot, p = lm.p, i0 = p % n, i1 = p / n;
   const int64_t ncell = int64_t(Nc) * Nc * Nc;
   const int64_t cell = int64_t(blk) * CPB + lc;
-  const bool inblk = lc < CPB;
+  const bool inblk = lm.used;
   const bool active = inblk && cell < ncell;
   int cx = 0, cy = 0, cz = 0;
   if (active) {
@@ -123,7 +135,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
       Rc[l * n2 + p] = out[l];
     }
   }
-  __syncthreads();
+  cell_sync<WL>();
   // phase y: lanes own y-lines (x = i0, z = i1)
   if (inblk) {
     T u[n], ul[n], ur[n], out[n];
@@ -140,7 +152,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
 #pragma unroll
     for (int b = 0; b < n; ++b) Rc[i1 * n2 + b * n + i0] += out[b];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // phase x: lanes own x-lines (y = i0, z = i1); the sum of the three directions is stored
   if (inblk) {
     T u[n], ul[n], ur[n], out[n];
@@ -164,7 +176,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
 
 template <int K, typename T>
 hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStream_t s) {
-  constexpr int CPB = kBlock / ((K + 1) * (K + 1));
+  constexpr int CPB = DGLanes<K>::cpb;
   const int grid = int((L.ncells + CPB - 1) / CPB);
   const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
   sipg_kernel<K, T><<<grid, kBlock, 0, s>>>(src, dst, L.Nc, T(L.h), T(sigma),
@@ -391,12 +403,14 @@ __global__ void __launch_bounds__(kBlock)
 dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const T *__restrict__ ax,
                      const T *__restrict__ dpinv, T *__restrict__ d, T *__restrict__ x,
                      double *__restrict__ x64, int64_t ncells, T c1, T c2) {
-  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = kBlock / n2;
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = DGLanes<K>::cpb;
+  constexpr bool WL = DGLanes<K>::wave;
   constexpr const EOTab<n, T> &eo = ct::Tables<n, T>::eo;
   __shared__ T U[CPB * n3], V[CPB * n3];
-  const int t = threadIdx.x, lc = t / n2, p = t - lc * n2, i0 = p % n, i1 = p / n;
+  const LaneMap<n2, WL> lm(threadIdx.x, CPB);
+  const int lc = lm.slot, p = lm.p, i0 = p % n, i1 = p / n;
   const int64_t cell = int64_t(xcd_block(blockIdx.x, gridDim.x)) * CPB + lc;
-  const bool inblk = lc < CPB;
+  const bool inblk = lm.used;
   const bool active = inblk && cell < ncells;
   const int slot = inblk ? lc : 0;
   T *Uc = U + slot * n3, *Vc = V + slot * n3;
@@ -419,7 +433,7 @@ dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const 
 #pragma unroll
     for (int l = 0; l < n; ++l) Uc[l * n2 + p] = r[l];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // phase 2: y-lines (x = i0, z = i1): S^T along y
   if (inblk) {
     T w[n], r[n];
@@ -429,7 +443,7 @@ dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const 
 #pragma unroll
     for (int b = 0; b < n; ++b) Vc[i1 * n2 + b * n + i0] = r[b];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // phase 3: x-lines (y = i0, z = i1): S^T along x, D'^{-1}, S along x
   if (inblk) {
     T w[n], r[n];
@@ -442,7 +456,7 @@ dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const 
 #pragma unroll
     for (int a = 0; a < n; ++a) Uc[i1 * n2 + i0 * n + a] = w[a];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // phase 4: y-lines: S along y
   if (inblk) {
     T w[n], r[n];
@@ -452,7 +466,7 @@ dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const 
 #pragma unroll
     for (int b = 0; b < n; ++b) Vc[i1 * n2 + b * n + i0] = r[b];
   }
-  __syncthreads();
+  cell_sync<WL>();
   // phase 5: z-lines: S along z, then the update of the lane's z-line
   if (active) {
     T w[n], cw[n];
@@ -572,7 +586,7 @@ hipError_t launch_sipg_gll_jacobi_diag(const Context &c, const Level &L, hipStre
 template <int K, typename A, typename T, int MODE>
 static hipError_t dg_gll_k(const Level &L, const void *b_in, void *b_store, const void *ax, const void *dpinv,
                            void *d, void *x, double *x64, double c1, double c2, hipStream_t s) {
-  constexpr int CPB = kBlock / ((K + 1) * (K + 1));
+  constexpr int CPB = DGLanes<K>::cpb;
   const int grid = int((L.ncells + CPB - 1) / CPB);
   dg_gll_jacobi_kernel<K, A, T, MODE><<<grid, kBlock, 0, s>>>(
       (const A *)b_in, (T *)b_store, (const T *)ax, (const T *)dpinv, (T *)d, (T *)x, x64, L.ncells, T(c1), T(c2));
