@@ -319,6 +319,7 @@ def main():
     y64 = torch.empty_like(u64)
     ms_step, kern_ms, launches = time_applies(prob, u64, y64, args.steps, args.warmup)
     protocol = repetitions(prob, u64, y64)
+    traffic = measured_traffic()
     bytes64 = apply_bytes(n, cells, q, 8)
     achieved = bytes64 / (kern_ms * 1e-3) / 1e9
 
@@ -348,10 +349,12 @@ def main():
                    "degree": k, "cells_per_dim": Nc, "n_dofs": n, "geometry": "x+0.1 sin sin sin",
                    "quadrature": "Gauss %d^3" % (k + 1), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "measured_GBs": None if traffic is None else traffic / (kern_ms * 1e-3) / 1e9,
                      "kernel": "apply_brick_kernel<4,double,curved>", "kernel_ms": kern_ms,
                      "algorithmic_bytes": bytes64, "timed_launches": launches,
                      "kernel_source_hash": kernel_source_hash()},
+        "equiv_dofs_per_s": cells * k ** 3 / (ms_step * 1e-3),
         "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32,
                        "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
                        "frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
