@@ -166,12 +166,14 @@ struct Tables {
 // reference stiffness Kg[i][j] = sum_q w_q psi_i'(x_q) psi_j'(x_q) in even-odd form and its
 // diagonal kgd, and the basis values and derivatives at the end points: fv0[i] = psi_i(0),
 // fd0[i] = psi_i'(0).  By the symmetry of the points, psi_i(1) = fv0[N-1-i] and
-// psi_i'(1) = -fd0[N-1-i].
+// psi_i'(1) = -fd0[N-1-i].  Even and odd halves of the end-point rows for i < N/2:
+// fe = (fv0[i] + fv0[N-1-i]) / 2, fo = (fv0[i] - fv0[N-1-i]) / 2, and de, dd alike from fd0.
 template <int N, typename T>
 struct DGTab {
   T xg[N], w[N];
   T fv0[N], fd0[N];
   T kgd[N];
+  T fe[N / 2 + 1], fo[N / 2 + 1], de[N / 2 + 1], dd[N / 2 + 1];
   EO<N, T> Kg;
 };
 
@@ -195,6 +197,13 @@ constexpr DGTab<N, T> dgtab() {
     const LegVal v = lagrange<N>(r.xg, i, 0.0);
     t.fv0[i] = T(v.P);
     t.fd0[i] = T(v.dP);
+  }
+  for (int i = 0; i < N / 2; ++i) {
+    const LegVal a = lagrange<N>(r.xg, i, 0.0), b = lagrange<N>(r.xg, N - 1 - i, 0.0);
+    t.fe[i] = T(0.5 * (a.P + b.P));
+    t.fo[i] = T(0.5 * (a.P - b.P));
+    t.de[i] = T(0.5 * (a.dP + b.dP));
+    t.dd[i] = T(0.5 * (a.dP - b.dP));
   }
   t.Kg = to_eo<N, T>(Kg);
   return t;

@@ -34,61 +34,126 @@ struct DGLanes {
   static constexpr int cpb = wave ? (kBlock / 64) * (64 / n2) : kBlock / n2;   // cells per block
 };
 
-// t = scale * A1-part of one line: cell term K_g u / h plus the two faces of the cell along
-// this direction (face 0 at xi = 0 with outward normal -1, face 1 at xi = 1 with +1).
+// out = scale * A1-part of one line: the cell term K_g u / h plus the two faces of the cell
+// along this direction (face 0 at xi = 0 with outward normal -1, face 1 at xi = 1 with +1).
+// Per face, with own and neighbour end-point values v-, v+ and derivatives d-, d+:
+//   jump = v- - v+,  avg = sign (d- + d+) / (2h),
+//   cv = -avg + sigma jump (tests by value),  cg = -sign jump / (2h) (tests by derivative),
+//   t_i += cv psi_i(face) + cg psi_i'(face).
 // uL / uR: the neighbour cells' lines (used when hasL / hasR); without a neighbour the face
-// is a boundary face: Dirichlet mirror u+ = -u-, grad u+ = grad u- (jump 2u-, average
+// is a boundary face: Dirichlet mirror u+ = -u-, grad u+ = grad u- (jump 2 v-, average
 // derivative = own derivative), or homogeneous Neumann (no contribution).
+// The cell term and both faces are evaluated in even-odd form: by the symmetry of the Gauss
+// points the own end-point values of the two faces are E +- O of one even and one odd sum
+// over u_i +- u_{N-1-i}, and the face updates split the same way, so that they add to the
+// even and odd parts of K_g u before those are recombined.
 template <int N, typename T>
 __device__ __forceinline__ void sipg_line(const ct::DGTab<N, T> &tb, const T *u, const T *uL, bool hasL,
                                           const T *uR, bool hasR, T inv_h, T sigma, int dmask,
                                           T scale, T *out) {
-  T t[N];
-  eo_apply<N, 1>(tb.Kg, u, t);
+  constexpr int H = N / 2;
+  constexpr bool ODD = N & 1;
+  T e[H], o[H];
 #pragma unroll
-  for (int i = 0; i < N; ++i) t[i] *= inv_h;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const T sign = s ? T(1) : T(-1);
-    const bool has = s ? hasR : hasL;
-    const T *un = s ? uR : uL;
-    // own end-point value and derivative at xi = s; neighbour's at xi = 1 - s
-    T vm = 0, dm = 0, vp = 0, dp = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const T fvo = s ? tb.fv0[N - 1 - i] : tb.fv0[i];
-      const T fdo = s ? -tb.fd0[N - 1 - i] : tb.fd0[i];
-      const T fvn = s ? tb.fv0[i] : tb.fv0[N - 1 - i];
-      const T fdn = s ? tb.fd0[i] : -tb.fd0[N - 1 - i];
-      vm += fvo * u[i];
-      dm += fdo * u[i];
-      vp += fvn * un[i];
-      dp += fdn * un[i];
-    }
-    T jump, avg;
-    if (has) {
-      jump = vm - vp;
-      avg = T(0.5) * sign * (dm + dp) * inv_h;
-    } else if ((dmask >> s) & 1) {
-      jump = T(2) * vm;
-      avg = sign * dm * inv_h;
-    } else {
-      jump = 0;
-      avg = 0;
-    }
-    // test by value: -{n.grad u} + sigma [u];  test by normal derivative: -[u]/2
-    const T cv = -avg + sigma * jump;
-    const T cg = T(-0.5) * jump * sign * inv_h;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const T fvo = s ? tb.fv0[N - 1 - i] : tb.fv0[i];
-      const T fdo = s ? -tb.fd0[N - 1 - i] : tb.fd0[i];
-      t[i] += cv * fvo + cg * fdo;
-    }
+  for (int i = 0; i < H; ++i) {
+    e[i] = u[i] + u[N - 1 - i];
+    o[i] = u[i] - u[N - 1 - i];
   }
+  // own end-point values (vm0, vm1) and derivatives (dm0, dm1) at xi = 0, 1
+  T VE = ODD ? tb.fv0[H] * u[H] : T(0), DE = ODD ? tb.fd0[H] * u[H] : T(0), VO = 0, DO = 0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) out[i] = scale * t[i];
+  for (int i = 0; i < H; ++i) {
+    VE += tb.fe[i] * e[i];
+    VO += tb.fo[i] * o[i];
+    DE += tb.de[i] * e[i];
+    DO += tb.dd[i] * o[i];
+  }
+  const T vm0 = VE + VO, vm1 = VE - VO, dm0 = DE + DO, dm1 = DO - DE;
+  // neighbour end-point values at the shared faces: the left neighbour's xi = 1, the right
+  // neighbour's xi = 0
+  T vp0 = 0, dp0 = 0, vp1 = 0, dp1 = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    vp0 += tb.fv0[N - 1 - i] * uL[i];
+    dp0 -= tb.fd0[N - 1 - i] * uL[i];
+    vp1 += tb.fv0[i] * uR[i];
+    dp1 += tb.fd0[i] * uR[i];
+  }
+  const T hh = T(0.5) * inv_h;
+  T j0, a0, j1, a1;   // jumps and average normal derivatives (sign included)
+  if (hasL) {
+    j0 = vm0 - vp0;
+    a0 = -hh * (dm0 + dp0);
+  } else if (dmask & 1) {
+    j0 = T(2) * vm0;
+    a0 = -inv_h * dm0;
+  } else {
+    j0 = 0;
+    a0 = 0;
+  }
+  if (hasR) {
+    j1 = vm1 - vp1;
+    a1 = hh * (dm1 + dp1);
+  } else if (dmask & 2) {
+    j1 = T(2) * vm1;
+    a1 = inv_h * dm1;
+  } else {
+    j1 = 0;
+    a1 = 0;
+  }
+  const T cv0 = sigma * j0 - a0, cv1 = sigma * j1 - a1;
+  const T cg0 = hh * j0, cg1 = -hh * j1;
+  // scaled even / odd coefficients of the face updates
+  const T pe = scale * (cv0 + cv1), qe = scale * (cg0 - cg1);
+  const T po = scale * (cv0 - cv1), qo = scale * (cg0 + cg1);
+  const T sk = scale * inv_h;
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    T ev = ODD ? tb.Kg.ec[q] * u[H] : T(0), od = 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      ev += tb.Kg.ep[q * H + i] * e[i];
+      od += tb.Kg.op[q * H + i] * o[i];
+    }
+    const T EV = sk * ev + pe * tb.fe[q] + qe * tb.de[q];
+    const T OD = sk * od + po * tb.fo[q] + qo * tb.dd[q];
+    out[q] = EV + OD;
+    out[N - 1 - q] = EV - OD;
+  }
+  if constexpr (ODD) {
+    T m = tb.Kg.mid[H] * u[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) m += tb.Kg.mid[i] * e[i];
+    out[H] = sk * m + pe * tb.fv0[H] + qe * tb.fd0[H];
+  }
 }
+
+// Cell order of the SIPG kernel.  A cell reads its neighbours' lines across all six faces;
+// in plain x-fastest order the z neighbours are a whole plane of cells apart (7 MB for Q5 on
+// 64^3 cells, more than one XCD's 4 MB L2), so both z neighbours missed L2 and src was
+// fetched about three times (measured).  Instead the x-y plane is split into 2 x 4 column
+// tiles, one per XCD (work-groups are dispatched round-robin over the 8 XCDs), and each XCD
+// walks its column plane by plane, x fastest: the z neighbours are one tile plane apart and
+// stay in that XCD's L2.  Only the lines read across tile boundaries come from further out.
+struct ColumnOrder {
+  static constexpr int SX = 2, SY = 4;   // tiles per direction, SX * SY = number of XCDs
+  static int blocks_per_xcd(int Nc, int cpb) {
+    const int tx = (Nc + SX - 1) / SX, ty = (Nc + SY - 1) / SY;
+    return (tx * ty * Nc + cpb - 1) / cpb;
+  }
+  // cell coordinates of position t of the XCD's traversal; false past its last cell
+  __device__ static bool cell(int xcd, int t, int Nc, int &cx, int &cy, int &cz) {
+    const int ix = xcd % SX, iy = xcd / SX;
+    const int x0 = ix * Nc / SX, x1 = (ix + 1) * Nc / SX, y0 = iy * Nc / SY, y1 = (iy + 1) * Nc / SY;
+    const int tx = x1 - x0, area = tx * (y1 - y0);
+    if (t >= area * Nc) return false;   // also for an empty tile (area 0)
+    cz = t / area;
+    const int r = t - cz * area;
+    cy = y0 + r / tx;
+    cx = x0 + r - (r / tx) * tx;
+    return true;
+  }
+};
 
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -97,25 +162,21 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
   constexpr bool WL = DGLanes<K>::wave;
   constexpr const ct::DGTab<n, T> &tb = ct::DGTables<n, T>::tab;
   __shared__ T U[CPB * n3], R[CPB * n3];
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
   const LaneMap<n2, WL> lm(threadIdx.x, CPB);
   const int lc = lm.slot, p = lm.p, i0 = p % n, i1 = p / n;
-  const int64_t ncell = int64_t(Nc) * Nc * Nc;
-  const int64_t cell = int64_t(blk) * CPB + lc;
   const bool inblk = lm.used;
-  const bool active = inblk && cell < ncell;
   int cx = 0, cy = 0, cz = 0;
-  if (active) {
-    cx = int(cell % Nc);
-    cy = int((cell / Nc) % Nc);
-    cz = int(cell / (int64_t(Nc) * Nc));
-  }
+  const bool active = inblk && ColumnOrder::cell(blockIdx.x % 8, (blockIdx.x / 8) * CPB + lc, Nc, cx, cy, cz);
+  const int64_t cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
   const T inv_h = T(1) / h;
   const T scale = h * h * tb.w[i0] * tb.w[i1];   // tangential weights of every phase
   const int slot = inblk ? lc : 0;
   T *Uc = U + slot * n3, *Rc = R + slot * n3;
   const T *uc = src + cell * n3;
   const int64_t plane = int64_t(Nc) * Nc;
+  // Loads are unconditional: every pointer below addresses a cell of src (an inactive lane
+  // reads cell 0, a missing neighbour the cell itself), and sipg_line ignores the neighbour
+  // line of a boundary face.  Guarded loads would become one branch each.
 
   // phase z: lanes own z-lines (x = i0, y = i1)
   if (inblk) {
@@ -124,9 +185,9 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
     const T *pl = src + (hasL ? cell - plane : cell) * n3, *pr = src + (hasR ? cell + plane : cell) * n3;
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-      u[l] = active ? uc[l * n2 + p] : T(0);
-      ul[l] = (active && hasL) ? pl[l * n2 + p] : T(0);
-      ur[l] = (active && hasR) ? pr[l * n2 + p] : T(0);
+      u[l] = uc[l * n2 + p];
+      ul[l] = pl[l * n2 + p];
+      ur[l] = pr[l * n2 + p];
     }
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
 #pragma unroll
@@ -145,8 +206,8 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
     for (int b = 0; b < n; ++b) {
       const int o = i1 * n2 + b * n + i0;
       u[b] = Uc[o];
-      ul[b] = (active && hasL) ? pl[o] : T(0);
-      ur[b] = (active && hasR) ? pr[o] : T(0);
+      ul[b] = pl[o];
+      ur[b] = pr[o];
     }
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
 #pragma unroll
@@ -162,8 +223,8 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
     for (int a = 0; a < n; ++a) {
       const int o = i1 * n2 + i0 * n + a;
       u[a] = Uc[o];
-      ul[a] = (active && hasL) ? pl[o] : T(0);
-      ur[a] = (active && hasR) ? pr[o] : T(0);
+      ul[a] = pl[o];
+      ur[a] = pr[o];
     }
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
     if (active) {
@@ -177,7 +238,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
 template <int K, typename T>
 hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStream_t s) {
   constexpr int CPB = DGLanes<K>::cpb;
-  const int grid = int((L.ncells + CPB - 1) / CPB);
+  const int grid = 8 * ColumnOrder::blocks_per_xcd(L.Nc, CPB);
   const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
   sipg_kernel<K, T><<<grid, kBlock, 0, s>>>(src, dst, L.Nc, T(L.h), T(sigma),
                                            dirichlet_mask(c.p));
