@@ -35,20 +35,21 @@ struct Shape {
   static constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, cpb = kBlock / n2;
 };
 
-// Cells per chunk in x, y, z for degree K, chunks per brick along x, and the lane layout:
+// Cells per chunk in x, y, z for degree K, chunks per brick along x (chunks), y (ny) and z
+// (nz), and the lane layout:
 // wave = true places every cell's n^2 lanes inside one wavefront (64 / n^2 cells per
 // wavefront, four wavefronts per work-group), so the phases of a cell need no work-group
 // barrier; wave = false packs the cells densely over the work-group (cells may straddle
 // wavefronts; required for n^2 > 64).
 template <int K> struct Brick;
-template <> struct Brick<1> { static constexpr int x = 4, y = 4, z = 4, chunks = 1; static constexpr bool wave = true; };
-template <> struct Brick<2> { static constexpr int x = 3, y = 3, z = 3, chunks = 1; static constexpr bool wave = true; };
-template <> struct Brick<3> { static constexpr int x = 4, y = 2, z = 2, chunks = 2; static constexpr bool wave = true; };
-template <> struct Brick<4> { static constexpr int x = 2, y = 2, z = 2, chunks = 4; static constexpr bool wave = true; };
-template <> struct Brick<5> { static constexpr int x = 3, y = 2, z = 1, chunks = 2; static constexpr bool wave = false; };
-template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; static constexpr bool wave = true; };
-template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2; static constexpr bool wave = true; };
-template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2; static constexpr bool wave = false; };
+template <> struct Brick<1> { static constexpr int x = 4, y = 4, z = 4, chunks = 1, ny = 1, nz = 1; static constexpr bool wave = true; };
+template <> struct Brick<2> { static constexpr int x = 3, y = 3, z = 3, chunks = 1, ny = 1, nz = 1; static constexpr bool wave = true; };
+template <> struct Brick<3> { static constexpr int x = 4, y = 2, z = 2, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = true; };
+template <> struct Brick<4> { static constexpr int x = 2, y = 2, z = 2, chunks = 4, ny = 1, nz = 1; static constexpr bool wave = true; };
+template <> struct Brick<5> { static constexpr int x = 3, y = 2, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = false; };
+template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = true; };
+template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = true; };
+template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = false; };
 
 struct CellCtx {
   int i0, i1;        // lane coordinates within the cell
@@ -348,8 +349,9 @@ __device__ __forceinline__ int halo_index(int X, int Y, int Z, int MX, int MY, i
 }
 
 // dst = A src for CG Q_K, one brick per work-group.  The work-group walks the chunks of its
-// brick; every lane holds the src line (and, on curved meshes, the metric and kappa) of its
-// cell of the next chunk in registers, loaded while the current chunk is computed.
+// brick (x fastest, then y, then z; chunks outside the mesh are skipped); every lane holds
+// the src line (and, on curved meshes, the metric and kappa) of its cell of the next chunk
+// in registers, loaded while the current chunk is computed.
 template <int K, typename T, bool CURVED>
 __global__ void __launch_bounds__(kBlock)
 apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ halo,
@@ -358,11 +360,12 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   using S = Shape<K>;
   using Bk = Brick<K>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
-  constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ, NCH = Bk::chunks;
+  constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ;
+  constexpr int NCX = Bk::chunks, NCY = Bk::ny, NCZ = Bk::nz, NCH = NCX * NCY * NCZ;
   constexpr bool WL = Bk::wave;
   static_assert(WL ? (n2 <= 64 && CPB <= (kBlock / 64) * (64 / n2)) : CPB * n2 <= kBlock,
                 "chunk does not fit the work-group");
-  constexpr int MX = NCH * CX * K, MY = BY * K, MZ = BZ * K;   // brick extent in DoF intervals
+  constexpr int MX = NCX * CX * K, MY = NCY * BY * K, MZ = NCZ * BZ * K;   // brick extent in DoF intervals
   constexpr int TX = MX + 1, TY = MY + 1, TZ = MZ + 1;
   constexpr int NBUF = CURVED ? 3 : 4;
   constexpr int ITEMS = TX * TY * TZ, ITERS = (ITEMS + kBlock - 1) / kBlock;
@@ -377,14 +380,16 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   const int lx = lc % CX, ly = (lc / CX) % BY, lz = lc / (CX * BY);
   const bool inblk = lm.used;
   const int Nc = bg.Nc, N1 = bg.N1;
-  const int cx0 = bx * NCH * CX, cy = by * BY + ly, cz = bz * BZ + lz;
-  const int nchunks = min(NCH, (Nc - cx0 + CX - 1) / CX);
+  const int cx0 = bx * NCX * CX, cy0 = by * NCY * BY, cz0 = bz * NCZ * BZ;
+  // chunks per direction that hold cells of the mesh
+  const int ncx = min(NCX, (Nc - cx0 + CX - 1) / CX), ncy = min(NCY, (Nc - cy0 + BY - 1) / BY),
+            ncz = min(NCZ, (Nc - cz0 + BZ - 1) / BZ);
   T *A = sm[0] + lc * n3, *B = sm[1] + lc * n3, *C = sm[2] + lc * n3;
 
-  // the lane's cell in chunk j (inactive past the brick's last chunk)
-  auto cell_at = [&](int j, CellCtx &cc, int64_t &cell) {
-    const int cx = cx0 + j * CX + lx;
-    const bool active = inblk && j < nchunks && cx < Nc && cy < Nc && cz < Nc;
+  // the lane's cell in chunk (jx, jy, jz) (inactive for jx < 0: no chunk)
+  auto cell_at = [&](int jx, int jy, int jz, CellCtx &cc, int64_t &cell) {
+    const int cx = cx0 + jx * CX + lx, cy = cy0 + jy * BY + ly, cz = cz0 + jz * BZ + lz;
+    const bool active = inblk && jx >= 0 && cx < Nc && cy < Nc && cz < Nc;
     cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
     cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, bg.dmask);
   };
@@ -398,7 +403,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
 
   CellCtx cc;
   int64_t cell;
-  cell_at(0, cc, cell);
+  cell_at(0, 0, 0, cc, cell);
   T u[n];
   T g[6][CURVED ? n : 1];
   gather_zline(cc, src, u);
@@ -407,11 +412,16 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
 
 #pragma unroll
   for (int j = 0; j < NCH; ++j) {
-    if (j >= nchunks) break;
+    const int jx = j % NCX, jy = (j / NCX) % NCY, jz = j / (NCX * NCY);
+    if (jx >= ncx || jy >= ncy || jz >= ncz) continue;
+    // the next chunk of the walk that holds cells
+    const int nx = jx + 1 < ncx ? jx + 1 : (jy + 1 < ncy || jz + 1 < ncz ? 0 : -1);
+    const int ny = jx + 1 < ncx ? jy : (jy + 1 < ncy ? jy + 1 : 0);
+    const int nz = jx + 1 < ncx || jy + 1 < ncy ? jz : jz + 1;
     CellCtx cn;
     int64_t celln;
-    cell_at(j + 1, cn, celln);
-    double *ctile = tile + (lz * K) * (TX * TY) + (ly * K) * TX + (j * CX + lx) * K;
+    cell_at(nx, ny, nz, cn, celln);
+    double *ctile = tile + ((jz * BZ + lz) * K) * (TX * TY) + ((jy * BY + ly) * K) * TX + (jx * CX + lx) * K;
     if constexpr (CURVED) {
       curved_cell<K, T, TX, TY, WL>(
           cc, u, g, kap, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
@@ -439,64 +449,100 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   // Dirichlet DoFs get the identity-row value src.
   const bool lastx = bx == bg.nbx - 1, lasty = by == bg.nby - 1, lastz = bz == bg.nbz - 1;
   const int64_t plane = int64_t(N1) * N1;
-  const int gx0 = cx0 * K, gy0 = by * MY, gz0 = bz * MZ;
+  const int gx0 = cx0 * K, gy0 = cy0 * K, gz0 = cz0 * K;
   const int64_t gbase = gx0 + int64_t(N1) * gy0 + plane * gz0;
   // interior bricks without Dirichlet DoFs and without cut-off cells need no per-item tests
   const bool plain = gx0 + MX < N1 - 1 && gy0 + MY < N1 - 1 && gz0 + MZ < N1 - 1 &&
                      !((bg.dmask & 1) && (gx0 == 0 || gy0 == 0 || gz0 == 0));
   constexpr int OWN = MX * MY * MZ, ITO = (OWN + kBlock - 1) / kBlock;
+  constexpr int HS = (MY + 1) * (MZ + 1) + MX * (MZ + 1) + MX * MY, ITH = (HS + kBlock - 1) / kBlock;
+  T *hrec = halo + int64_t(brick) * HS;
+  // tile position of halo record item i (layout of halo_index)
+  auto halo_item = [&](int i, int &X, int &Y, int &Z) {
+    if (i < (MY + 1) * (MZ + 1)) {
+      X = MX;
+      Y = i % (MY + 1);
+      Z = i / (MY + 1);
+    } else if (i < (MY + 1) * (MZ + 1) + MX * (MZ + 1)) {
+      const int q = i - (MY + 1) * (MZ + 1);
+      X = q % MX;
+      Y = MY;
+      Z = q / MX;
+    } else {
+      const int q = i - (MY + 1) * (MZ + 1) - MX * (MZ + 1);
+      X = q % MX;
+      Y = q / MX;
+      Z = MZ;
+    }
+  };
+  if (plain) {
+    // Interior brick: every owned item goes to dst and every face item to the halo record.
+    // These loops hold stores only; a load in the same loop (the Dirichlet values below)
+    // makes the compiler wait for every store to complete before the next item.
+#pragma unroll
+    for (int it = 0; it < ITO; ++it) {
+      const int i = t + it * kBlock;
+      if (OWN % kBlock == 0 || i < OWN) {
+        const int X = i % MX, Y = (i / MX) % MY, Z = i / (MX * MY);
+        dst[gbase + (X + N1 * Y) + plane * Z] = T(tile[X + TX * (Y + TY * Z)]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITH; ++it) {
+      const int i = t + it * kBlock;
+      if (HS % kBlock == 0 || i < HS) {
+        int X, Y, Z;
+        halo_item(i, X, Y, Z);
+        hrec[i] = T(tile[X + TX * (Y + TY * Z)]);
+      }
+    }
+    return;
+  }
+  // Boundary brick: items outside the mesh are skipped and Dirichlet DoFs take the value of
+  // src.  The src values are loaded for all items first (from DoF 0 for items outside the
+  // mesh), so that the stores do not wait one by one.
+  T so[ITO], sh[ITH];
+#pragma unroll
+  for (int it = 0; it < ITO; ++it) {
+    const int i = t + it * kBlock;
+    const int X = i % MX, Y = (i / MX) % MY, Z = i / (MX * MY);
+    const bool in = (OWN % kBlock == 0 || i < OWN) && gx0 + X < N1 && gy0 + Y < N1 && gz0 + Z < N1;
+    so[it] = src[in ? gbase + (X + N1 * Y) + plane * Z : 0];
+  }
+#pragma unroll
+  for (int it = 0; it < ITH; ++it) {
+    const int i = t + it * kBlock;
+    int X, Y, Z;
+    halo_item(i, X, Y, Z);
+    const bool in = (HS % kBlock == 0 || i < HS) && gx0 + X < N1 && gy0 + Y < N1 && gz0 + Z < N1;
+    sh[it] = src[in ? gbase + (X + N1 * Y) + plane * Z : 0];
+  }
 #pragma unroll
   for (int it = 0; it < ITO; ++it) {
     const int i = t + it * kBlock;
     if (OWN % kBlock == 0 || i < OWN) {
       const int X = i % MX, Y = (i / MX) % MY, Z = i / (MX * MY);
-      const int64_t gi = gbase + (X + N1 * Y) + plane * Z;
-      const T v = T(tile[X + TX * (Y + TY * Z)]);
-      if (plain) {
-        dst[gi] = v;
-      } else {
-        const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
-        if (gx < N1 && gy < N1 && gz < N1) {
-          const bool bnd = dirichlet_dof(gx, gy, gz, N1, bg.dmask);
-          dst[gi] = bnd ? src[gi] : v;
-        }
+      const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
+      if (gx < N1 && gy < N1 && gz < N1) {
+        const T v = T(tile[X + TX * (Y + TY * Z)]);
+        dst[gbase + (X + N1 * Y) + plane * Z] = dirichlet_dof(gx, gy, gz, N1, bg.dmask) ? so[it] : v;
       }
     }
   }
-  constexpr int HS = (MY + 1) * (MZ + 1) + MX * (MZ + 1) + MX * MY, ITH = (HS + kBlock - 1) / kBlock;
-  T *hrec = halo + int64_t(brick) * HS;
 #pragma unroll
   for (int it = 0; it < ITH; ++it) {
     const int i = t + it * kBlock;
     if (HS % kBlock == 0 || i < HS) {
-      // decode the record index (layout of halo_index)
       int X, Y, Z;
-      if (i < (MY + 1) * (MZ + 1)) {
-        X = MX;
-        Y = i % (MY + 1);
-        Z = i / (MY + 1);
-      } else if (i < (MY + 1) * (MZ + 1) + MX * (MZ + 1)) {
-        const int q = i - (MY + 1) * (MZ + 1);
-        X = q % MX;
-        Y = MY;
-        Z = q / MX;
-      } else {
-        const int q = i - (MY + 1) * (MZ + 1) - MX * (MZ + 1);
-        X = q % MX;
-        Y = q / MX;
-        Z = MZ;
-      }
+      halo_item(i, X, Y, Z);
       const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
       if (gx < N1 && gy < N1 && gz < N1) {
         const T v = T(tile[X + TX * (Y + TY * Z)]);
         const bool is_halo = (X == MX && !lastx) || (Y == MY && !lasty) || (Z == MZ && !lastz);
-        if (is_halo) {
+        if (is_halo)
           hrec[i] = v;
-        } else {
-          const int64_t gi = gbase + (X + N1 * Y) + plane * Z;
-          const bool bnd = dirichlet_dof(gx, gy, gz, N1, bg.dmask);
-          dst[gi] = bnd ? src[gi] : v;
-        }
+        else
+          dst[gbase + (X + N1 * Y) + plane * Z] = dirichlet_dof(gx, gy, gz, N1, bg.dmask) ? sh[it] : v;
       }
     }
   }
@@ -510,7 +556,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
 halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
-  constexpr int MY = Brick<K>::y * K, MZ = Brick<K>::z * K;
+  constexpr int MY = Brick<K>::y * Brick<K>::ny * K, MZ = Brick<K>::z * Brick<K>::nz * K;
   const int MX = bg.sx * K;
   const unsigned N1 = bg.N1, P = N1 * N1;
   const unsigned fx = unsigned(bg.nbx - 1) * P, fy = unsigned(bg.nby - 1) * P,
@@ -639,8 +685,8 @@ BrickGrid brick_grid(int Nc, int N1, int dmask) {
   bg.N1 = N1;
   bg.sx = Brick<K>::x * Brick<K>::chunks;
   bg.nbx = (Nc + bg.sx - 1) / bg.sx;
-  bg.nby = (Nc + Brick<K>::y - 1) / Brick<K>::y;
-  bg.nbz = (Nc + Brick<K>::z - 1) / Brick<K>::z;
+  bg.nby = (Nc + Brick<K>::y * Brick<K>::ny - 1) / (Brick<K>::y * Brick<K>::ny);
+  bg.nbz = (Nc + Brick<K>::z * Brick<K>::nz - 1) / (Brick<K>::z * Brick<K>::nz);
   bg.dmask = dmask;
   return bg;
 }
@@ -652,8 +698,8 @@ int64_t cg_halo_elements(int k, int Nc) {
   int my = 0, mz = 0;
 #define CASE(K)                              \
   bg = brick_grid<K>(Nc, K * Nc + 1, 3);     \
-  my = Brick<K>::y * K;                      \
-  mz = Brick<K>::z * K;                      \
+  my = Brick<K>::y * Brick<K>::ny * K;       \
+  mz = Brick<K>::z * Brick<K>::nz * K;       \
   break
   switch (k) {
     case 1: CASE(1);
