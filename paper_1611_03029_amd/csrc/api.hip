@@ -118,7 +118,7 @@ int64_t layout(Context &c, char *base) {
       L.metric64 = b.take<double>(L.ncells * 6 * n3);
       L.metric32 = b.take<float>(L.ncells * 6 * n3);
     }
-    if (cg) L.halo = b.take<double>(cg_halo_elements(c.k, L.Nc));
+    if (cg) L.halo = b.take<double>(cg_halo_elements(c.k, L.Nc, p.geometry == MFL_GEOM_CURVED));
     {
       L.diag64 = b.take<double>(L.ndofs);
       L.dinv64 = b.take<double>(L.ndofs);

@@ -18,6 +18,7 @@
 // faces, which belong to neighbouring bricks, to the brick's halo record.  A second
 // kernel adds the halo records into the lower faces of each brick.  Deterministic; no
 // clearing pass.
+#include <algorithm>
 #include <cmath>
 
 #include "ct_tables.h"
@@ -50,6 +51,21 @@ template <> struct Brick<5> { static constexpr int x = 3, y = 2, z = 1, chunks =
 template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = true; };
 template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = true; };
 template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = false; };
+
+// Brick shape of the operator kernel for degree K, precision T and geometry: Brick<K> unless a
+// specialization below was measured faster.  On Cartesian cells (no metric stream) the
+// operator costs little per DoF and the halo of the brick faces takes a large share at low
+// degree; bricks that also span two chunks in y (and z) cut it (measured on 64^3 cells,
+// operator plus halo addition: Q2 -18% / -20% (FP64 / FP32), Q3 -9% / -3%, Q5 and Q6 FP64
+// -10% and -7%; the same shapes were slower for Q4 and for FP32 at Q5 and Q6).
+template <int K, typename T, bool CURVED>
+struct BrickShape : Brick<K> {};
+template <> struct BrickShape<2, float, false> : Brick<2> { static constexpr int chunks = 4, ny = 2, nz = 2; };
+template <> struct BrickShape<2, double, false> : Brick<2> { static constexpr int chunks = 2, ny = 2, nz = 2; };
+template <> struct BrickShape<3, float, false> : Brick<3> { static constexpr int chunks = 2, ny = 2, nz = 1; };
+template <> struct BrickShape<3, double, false> : Brick<3> { static constexpr int chunks = 2, ny = 2, nz = 1; };
+template <> struct BrickShape<5, double, false> : Brick<5> { static constexpr int chunks = 2, ny = 2, nz = 1; };
+template <> struct BrickShape<6, double, false> : Brick<6> { static constexpr int chunks = 2, ny = 2, nz = 1; };
 
 struct CellCtx {
   int i0, i1;        // lane coordinates within the cell
@@ -329,6 +345,7 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T (&u)[K + 
 struct BrickGrid {
   int Nc, N1;
   int sx;              // cells per brick in x (multiple of the chunk width)
+  int my, mz;          // brick extent in y and z in DoF intervals
   int nbx, nby, nbz;   // bricks per direction
   int dmask;           // Dirichlet face mask
 };
@@ -358,7 +375,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
                    const T *__restrict__ kappa, const T *__restrict__ metric, BrickGrid bg, T h) {
   constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
   using S = Shape<K>;
-  using Bk = Brick<K>;
+  using Bk = BrickShape<K, T, CURVED>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
   constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ;
   constexpr int NCX = Bk::chunks, NCY = Bk::ny, NCZ = Bk::nz, NCH = NCX * NCY * NCZ;
@@ -556,8 +573,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
 halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
-  constexpr int MY = Brick<K>::y * Brick<K>::ny * K, MZ = Brick<K>::z * Brick<K>::nz * K;
-  const int MX = bg.sx * K;
+  const int MX = bg.sx * K, MY = bg.my, MZ = bg.mz;
   const unsigned N1 = bg.N1, P = N1 * N1;
   const unsigned fx = unsigned(bg.nbx - 1) * P, fy = unsigned(bg.nby - 1) * P,
                  fz = unsigned(bg.nbz - 1) * P;
@@ -594,15 +610,26 @@ halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
       X[d] = g[d] - b[d] * M[d];
       sh[d] = X[d] == 0 && b[d] > 0;
     }
-    T s = 0;
-    for (int m = 1; m < 8; ++m) {
-      if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
+    // record entry of the lower brick across the shared directions in mask m
+    auto entry = [&](int m) {
       const int ob0 = b[0] - (m & 1), ob1 = b[1] - ((m >> 1) & 1), ob2 = b[2] - ((m >> 2) & 1);
       const int tx = (m & 1) ? MX : X[0], ty = (m & 2) ? MY : X[1], tz = (m & 4) ? MZ : X[2];
       const int64_t ob = ob0 + int64_t(bg.nbx) * (ob1 + int64_t(bg.nby) * ob2);
-      s += halo[ob * hs + halo_index(tx, ty, tz, MX, MY, MZ)];
+      return ob * hs + halo_index(tx, ty, tz, MX, MY, MZ);
+    };
+    // dst and the first record entry (every visited DoF lies on at least one face) are loaded
+    // together; edges and corners (3 and 7 entries) add the others in increasing m
+    const int64_t gi = g[0] + int64_t(N1) * (g[1] + int64_t(N1) * g[2]);
+    const int m0 = sh[0] ? 1 : (sh[1] ? 2 : 4);
+    const T d = dst[gi];
+    T s = halo[entry(m0)];
+    if (int(sh[0]) + int(sh[1]) + int(sh[2]) > 1) {
+      for (int m = m0 + 1; m < 8; ++m) {
+        if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
+        s += halo[entry(m)];
+      }
     }
-    dst[g[0] + int64_t(N1) * (g[1] + int64_t(N1) * g[2])] += s;
+    dst[gi] = d + s;
   }
 }
 
@@ -678,29 +705,34 @@ inline int grid_for(int64_t items, int cap = 65536) {
 // Bricks: chunk shape from Brick<K>; the x extent is a multiple of the chunk width chosen so
 // that there are about MFL_TARGET_BRICKS bricks (enough work-groups to fill the chip) when
 // the mesh allows, which keeps the strided x-face halos to a few planes.
-template <int K>
+template <int K, typename T, bool CURVED>
 BrickGrid brick_grid(int Nc, int N1, int dmask) {
+  using Bk = BrickShape<K, T, CURVED>;
   BrickGrid bg;
   bg.Nc = Nc;
   bg.N1 = N1;
-  bg.sx = Brick<K>::x * Brick<K>::chunks;
+  bg.sx = Bk::x * Bk::chunks;
+  bg.my = Bk::y * Bk::ny * K;
+  bg.mz = Bk::z * Bk::nz * K;
   bg.nbx = (Nc + bg.sx - 1) / bg.sx;
-  bg.nby = (Nc + Brick<K>::y * Brick<K>::ny - 1) / (Brick<K>::y * Brick<K>::ny);
-  bg.nbz = (Nc + Brick<K>::z * Brick<K>::nz - 1) / (Brick<K>::z * Brick<K>::nz);
+  bg.nby = (Nc + Bk::y * Bk::ny - 1) / (Bk::y * Bk::ny);
+  bg.nbz = (Nc + Bk::z * Bk::nz - 1) / (Bk::z * Bk::nz);
   bg.dmask = dmask;
   return bg;
 }
 
+template <int K, typename T, bool CURVED>
+int64_t halo_elements(int Nc) {
+  const BrickGrid bg = brick_grid<K, T, CURVED>(Nc, K * Nc + 1, 3);
+  return int64_t(bg.nbx) * bg.nby * bg.nbz * halo_size(bg.sx * K, bg.my, bg.mz);
+}
+
 }  // namespace
 
-int64_t cg_halo_elements(int k, int Nc) {
-  BrickGrid bg{};
-  int my = 0, mz = 0;
-#define CASE(K)                              \
-  bg = brick_grid<K>(Nc, K * Nc + 1, 3);     \
-  my = Brick<K>::y * Brick<K>::ny * K;       \
-  mz = Brick<K>::z * Brick<K>::nz * K;       \
-  break
+int64_t cg_halo_elements(int k, int Nc, bool curved) {
+#define CASE(K)                                                                                \
+  return curved ? std::max(halo_elements<K, double, true>(Nc), halo_elements<K, float, true>(Nc)) \
+                : std::max(halo_elements<K, double, false>(Nc), halo_elements<K, float, false>(Nc))
   switch (k) {
     case 1: CASE(1);
     case 2: CASE(2);
@@ -713,7 +745,6 @@ int64_t cg_halo_elements(int k, int Nc) {
     default: return 0;
   }
 #undef CASE
-  return int64_t(bg.nbx) * bg.nby * bg.nbz * halo_size(bg.sx * k, my, mz);
 }
 
 hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
@@ -730,20 +761,24 @@ hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, con
 template <int K, typename T>
 static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, T> &tab, const T *kappa,
                              const T *metric, const T *src, T *dst, T *halo, hipStream_t s, int dmask) {
-  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, dmask < 0 ? dirichlet_mask(c.p) : dmask);
-  const int nb = bg.nbx * bg.nby * bg.nbz;
+  const int dm = dmask < 0 ? dirichlet_mask(c.p) : dmask;
   (void)tab;
-  if (c.p.geometry == MFL_GEOM_CURVED)
-    apply_brick_kernel<K, T, true><<<nb, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
-  else
-    apply_brick_kernel<K, T, false><<<nb, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+  if (c.p.geometry == MFL_GEOM_CURVED) {
+    const BrickGrid bg = brick_grid<K, T, true>(L.Nc, L.N1, dm);
+    apply_brick_kernel<K, T, true><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
+  } else {
+    const BrickGrid bg = brick_grid<K, T, false>(L.Nc, L.N1, dm);
+    apply_brick_kernel<K, T, false><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+  }
   return hipGetLastError();
 }
 
 template <int K, typename T>
 static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *halo, hipStream_t s,
                             int dmask) {
-  const BrickGrid bg = brick_grid<K>(L.Nc, L.N1, dmask < 0 ? dirichlet_mask(c.p) : dmask);
+  const int dm = dmask < 0 ? dirichlet_mask(c.p) : dmask;
+  const BrickGrid bg = c.p.geometry == MFL_GEOM_CURVED ? brick_grid<K, T, true>(L.Nc, L.N1, dm)
+                                                       : brick_grid<K, T, false>(L.Nc, L.N1, dm);
   const int64_t total = int64_t(bg.nbx - 1 + bg.nby - 1 + bg.nbz - 1) * L.N1 * L.N1;
   if (total == 0) return hipSuccess;
   if (total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit face index space

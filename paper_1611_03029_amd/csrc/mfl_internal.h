@@ -154,7 +154,7 @@ hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const vo
                            hipStream_t s, int dmask = -1);
 hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s,
                               int dmask = -1);
-int64_t cg_halo_elements(int k, int Nc);
+int64_t cg_halo_elements(int k, int Nc, bool curved);
 hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *u, const double *lam,
                                 double *grad, hipStream_t s);
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s);

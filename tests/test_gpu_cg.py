@@ -62,6 +62,21 @@ def test_apply_ragged_bricks(k, Nc):
     assert rel_err(cart.apply(t(u)), o_cg.assemble(Box(Nc, k), kap) @ u) <= 1e-12
 
 
+@pytest.mark.parametrize("k,Nc,bc", [(2, 13, "dirichlet"), (2, 13, "mixed"), (3, 9, "dirichlet"),
+                                     (3, 9, "mixed"), (5, 7, "mixed"), (6, 5, "dirichlet")])
+def test_apply_cartesian_multi_brick(k, Nc, bc):
+    """Cartesian meshes that span several work-group bricks in every direction, with partial
+    bricks at the upper ends, for the taller Cartesian brick shapes of these degrees (halo
+    records in x, y and z, edges and corners), FP64 and FP32."""
+    box = Box(Nc, k)
+    kap = kappa_field(box.n_cells)
+    prob = mfl.Problem(k, Nc, kappa=kap, bc=mfl.MIXED if bc == "mixed" else mfl.DIRICHLET)
+    u = uniform_vector(box.n_dofs, 60 + k)
+    ref = o_cg.assemble(box, kap, bc=bc) @ u
+    assert rel_err(prob.apply(t(u)), ref) <= 1e-12
+    assert rel_err(prob.apply(t(u, torch.float32)).double(), ref) <= 2e-5
+
+
 @pytest.mark.parametrize("geom", [0.0, 0.1])
 def test_neumann_apply_and_null_space(geom):
     k, Nc = 3, 3
