@@ -207,7 +207,7 @@ void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b
 constexpr int kMaxProfiled = 8192;
 
 int apply_level(Context &c, int l, int dtype, const void *src, void *dst, hipStream_t s,
-                bool timed = false) {
+                bool timed = false, bool halo = true) {
   const Level &L = c.levels[l];
   const bool rec = timed && c.profiling && c.prof_used < kMaxProfiled;
   if (rec && c.prof_used == int(c.prof_start.size())) {
@@ -224,7 +224,7 @@ int apply_level(Context &c, int l, int dtype, const void *src, void *dst, hipStr
     HIP_TRY(launch_cg_apply(c, L, dtype, src, dst, s));
   }
   if (rec) HIP_TRY(hipEventRecord(c.prof_stop[c.prof_used++], s));
-  if (c.p.disc == MFL_DISC_CG) HIP_TRY(launch_cg_halo_add(c, L, dtype, dst, s));
+  if (c.p.disc == MFL_DISC_CG && halo) HIP_TRY(launch_cg_halo_add(c, L, dtype, dst, s));
   return MFL_OK;
 }
 
@@ -359,6 +359,25 @@ hipError_t cheb_step(const Context &c, Level &L, double *x64_out, int dt, double
   return launch_cheb_step(L.b, L.ax, dinv_of(L), L.d, L.x, x64_out, dt, L.ndofs, c1, c2, s);
 }
 
+// Continuous Q_k levels with 32-bit DoF indices take the halo addition of A x inside the
+// Chebyshev update (one streaming pass instead of two).
+bool fused_cheb(const Context &c, const Level &L) {
+  return c.p.disc == MFL_DISC_CG && L.ndofs < (int64_t(1) << 31);
+}
+
+// x += d with d = c1 d + c2 C (b - A x): the operator application and the update.
+int smoother_step(Context &c, int l, double *x64_out, int dt, double c1, double c2, hipStream_t s) {
+  Level &L = c.levels[l];
+  const bool fuse = fused_cheb(c, L);
+  if (const int rc = apply_level(c, l, dt, L.x, L.ax, s, false, !fuse)) return rc;
+  if (fuse) {
+    HIP_TRY(launch_cg_cheb_halo(c, L, L.b, L.ax, dinv_of(L), L.d, L.x, x64_out, dt, c1, c2, s));
+  } else {
+    HIP_TRY(cheb_step(c, L, x64_out, dt, c1, c2, s));
+  }
+  return MFL_OK;
+}
+
 // Chebyshev iteration on level l with interval [lo, hi] and `updates` updates of x.
 // zero_start: x = 0 initially and b is taken from b_in (stored into L.b when b_in != L.b).
 int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_start, const void *b_in,
@@ -379,15 +398,15 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
                                 1.0 / theta, s));
     if (updates == 1 && last_writes) HIP_TRY(launch_cast(L.x, dt, x64_out, MFL_F64, N, s));
   } else {
-    if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
-    HIP_TRY(cheb_step(c, L, (updates == 1) ? x64_out : nullptr, dt, 0.0, 1.0 / theta, s));
+    if ((rc = smoother_step(c, l, (updates == 1) ? x64_out : nullptr, dt, 0.0, 1.0 / theta, s))) return rc;
   }
   done = 1;
   double rho = delta > 0.0 ? delta / theta : 0.0;   // 1 / sigma_1
   for (; done < updates; ++done) {
     const double rho_new = 1.0 / (2.0 * theta / delta - rho);
-    if ((rc = apply_level(c, l, dt, L.x, L.ax, s))) return rc;
-    HIP_TRY(cheb_step(c, L, done + 1 == updates ? x64_out : nullptr, dt, rho_new * rho, 2.0 * rho_new / delta, s));
+    if ((rc = smoother_step(c, l, done + 1 == updates ? x64_out : nullptr, dt, rho_new * rho,
+                            2.0 * rho_new / delta, s)))
+      return rc;
     rho = rho_new;
   }
   return MFL_OK;

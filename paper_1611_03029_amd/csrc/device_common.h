@@ -26,6 +26,24 @@ __device__ __forceinline__ void lds_add(T *p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Division of 31-bit unsigned values by an invariant divisor d >= 1 with one 64-bit multiply
+// and a shift (division by invariant integers, Granlund and Montgomery 1994): with
+// L = ceil(log2 d) and m = ceil(2^(32+L) / d), q = floor(n m / 2^(32+L)) is exact for n < 2^31
+// because the rounding error of m times n stays below 2^(32+L) / d.
+struct FastDiv {
+  uint32_t d;
+  int shift;   // 32 + L
+  uint64_t m;
+  FastDiv() = default;
+  __host__ explicit FastDiv(uint32_t div) : d(div) {
+    int L = 0;
+    while ((uint64_t(1) << L) < div) ++L;
+    shift = 32 + L;
+    m = ((uint64_t(1) << shift) + div - 1) / div;
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const { return uint32_t((uint64_t(n) * m) >> shift); }
+};
+
 __device__ __forceinline__ bool on_boundary(int g, int N1) { return g == 0 || g == N1 - 1; }
 
 // Grid index g (0..N1-1) along one direction lies on a face with Dirichlet conditions:

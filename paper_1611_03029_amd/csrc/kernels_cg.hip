@@ -633,6 +633,61 @@ halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
   }
 }
 
+// Chebyshev update of the smoother fused with the halo addition (continuous Q_k), one DoF per
+// thread in memory order: ax = the brick kernel's value plus, on the lower faces of a brick,
+// the record entries of the 1, 3 or 7 lower bricks sharing the DoF (summed in the order of
+// halo_add_kernel), then d = c1 d + c2 dinv (b - ax) and x += d (and the FP64 copy of x when
+// x64 is given), as the plain Chebyshev update.  The face DoFs are no longer read and written
+// by a pass of their own.  32-bit DoF indices (checked on the host).
+struct DofDiv {
+  FastDiv n1, mx, my, mz;
+};
+
+template <int K, typename T>
+__global__ void __launch_bounds__(kBlock)
+cheb_halo_kernel(const T *__restrict__ ax, const T *__restrict__ halo, const T *__restrict__ b,
+                 const T *__restrict__ dinv, T *__restrict__ d, T *__restrict__ x,
+                 double *__restrict__ x64, BrickGrid bg, DofDiv dv, T c1, T c2) {
+  const int MX = bg.sx * K, MY = bg.my, MZ = bg.mz, N1 = bg.N1;
+  const uint32_t n = uint32_t(N1) * uint32_t(N1) * uint32_t(N1);
+  const int hs = halo_size(MX, MY, MZ);
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const uint32_t r = dv.n1.div(i), gz = dv.n1.div(r);
+    const int g[3] = {int(i - r * uint32_t(N1)), int(r - gz * uint32_t(N1)), int(gz)};
+    const int q[3] = {int(dv.mx.div(g[0])), int(dv.my.div(g[1])), int(dv.mz.div(g[2]))};
+    const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
+    int bb[3], X[3];
+    bool sh[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      bb[e] = min(q[e], NB[e] - 1);
+      X[e] = g[e] - bb[e] * M[e];
+      sh[e] = X[e] == 0 && bb[e] > 0;
+    }
+    T a = ax[i];
+    if ((sh[0] || sh[1] || sh[2]) && !dirichlet_dof(g[0], g[1], g[2], N1, bg.dmask)) {
+      auto entry = [&](int m) {
+        const int ob0 = bb[0] - (m & 1), ob1 = bb[1] - ((m >> 1) & 1), ob2 = bb[2] - ((m >> 2) & 1);
+        const int tx = (m & 1) ? MX : X[0], ty = (m & 2) ? MY : X[1], tz = (m & 4) ? MZ : X[2];
+        const int64_t ob = ob0 + int64_t(bg.nbx) * (ob1 + int64_t(bg.nby) * ob2);
+        return ob * hs + halo_index(tx, ty, tz, MX, MY, MZ);
+      };
+      const int m0 = sh[0] ? 1 : (sh[1] ? 2 : 4);
+      T sum = halo[entry(m0)];
+      for (int m = m0 + 1; m < 8; ++m) {
+        if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
+        sum += halo[entry(m)];
+      }
+      a = a + sum;
+    }
+    const T dn = c1 * d[i] + c2 * dinv[i] * (b[i] - a);
+    const T xn = x[i] + dn;
+    d[i] = dn;
+    x[i] = xn;
+    if (x64) x64[i] = double(xn);
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Per-cell gradient kernel: g_c = -lambda_c^T A_c^{(kappa=1)} u_c (CPB cells per group).
 template <int K, typename T, bool CURVED>
@@ -784,6 +839,35 @@ static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *h
   if (total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit face index space
   halo_add_kernel<K, T><<<grid_for(total, 16384), kBlock, 0, s>>>(dst, halo, bg);
   return hipGetLastError();
+}
+
+template <int K, typename T>
+static hipError_t cg_cheb_halo_k(const Context &c, const Level &L, const T *b, const T *ax, const T *dinv,
+                                 T *d, T *x, double *x64, double c1, double c2, hipStream_t s) {
+  const int dm = dirichlet_mask(c.p);
+  const BrickGrid bg = c.p.geometry == MFL_GEOM_CURVED ? brick_grid<K, T, true>(L.Nc, L.N1, dm)
+                                                       : brick_grid<K, T, false>(L.Nc, L.N1, dm);
+  if (L.ndofs >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit DoF index space
+  const DofDiv dv{FastDiv(uint32_t(L.N1)), FastDiv(uint32_t(bg.sx * K)), FastDiv(uint32_t(bg.my)),
+                  FastDiv(uint32_t(bg.mz))};
+  cheb_halo_kernel<K, T><<<grid_for(L.ndofs, 8192), kBlock, 0, s>>>(ax, (const T *)L.halo, b, dinv, d, x, x64, bg,
+                                                                    dv, T(c1), T(c2));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_cheb_halo(const Context &c, const Level &L, const void *b, const void *ax,
+                               const void *dinv, void *d, void *x, double *x64_out, int dtype, double c1,
+                               double c2, hipStream_t s) {
+  if (dtype == MFL_F64) {
+#define CASE(K) return cg_cheb_halo_k<K, double>(c, L, (const double *)b, (const double *)ax, (const double *)dinv, (double *)d, (double *)x, x64_out, c1, c2, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else {
+#define CASE(K) return cg_cheb_halo_k<K, float>(c, L, (const float *)b, (const float *)ax, (const float *)dinv, (float *)d, (float *)x, x64_out, c1, c2, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,

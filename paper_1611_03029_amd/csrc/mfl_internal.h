@@ -201,6 +201,11 @@ hipError_t launch_cheb_first(const void *b_in, int in_dtype, void *b_store, cons
 hipError_t launch_cheb_step(const void *b, const void *ax, const void *dinv, void *d, void *x,
                             double *x64_out, int dtype, int64_t n, double c1, double c2,
                             hipStream_t s);
+// The Chebyshev update fused with the halo addition of launch_cg_apply (continuous Q_k; ax
+// as left by launch_cg_apply without launch_cg_halo_add).
+hipError_t launch_cg_cheb_halo(const Context &c, const Level &L, const void *b, const void *ax,
+                               const void *dinv, void *d, void *x, double *x64_out, int dtype, double c1,
+                               double c2, hipStream_t s);
 hipError_t launch_prolongate_add(const Context &c, const Level &coarse, const Level &fine,
                                  const void *xc, int c_dtype, void *xf, int f_dtype, hipStream_t s);
 hipError_t launch_restrict_residual(const Context &c, const Level &coarse, const Level &fine,
