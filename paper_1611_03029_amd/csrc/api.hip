@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "mfl_internal.h"
@@ -132,6 +133,7 @@ int64_t layout(Context &c, char *base) {
       L.x = b.take<char>(L.ndofs * es);
       L.ax = b.take<char>(L.ndofs * es);
       L.d = b.take<char>(L.ndofs * es);
+      if (p.disc == MFL_DISC_SIPG && p.dg_jacobi_basis == MFL_DG_JACOBI_GLL) L.x2 = b.take<char>(L.ndofs * es);
     }
   }
   {
@@ -380,6 +382,9 @@ int smoother_step(Context &c, int l, double *x64_out, int dt, double c1, double 
 
 // Chebyshev iteration on level l with interval [lo, hi] and `updates` updates of x.
 // zero_start: x = 0 initially and b is taken from b_in (stored into L.b when b_in != L.b).
+// SIPG with the GLL Jacobi smoother fuses the operator into each update, which writes the
+// new x into the level's other x buffer; the buffers alternate and the result is copied back
+// into L.x after an odd number of such updates.
 int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_start, const void *b_in,
               int b_dtype, double *x64_out, hipStream_t s) {
   Level &L = c.levels[l];
@@ -389,6 +394,14 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
   int rc;
   int done = 0;
   const bool last_writes = x64_out != nullptr;
+  const bool dg_fused = gll_jacobi(c) && L.x2 != nullptr;
+  void *cur = L.x, *other = L.x2;
+  auto step = [&](double *x64, double c1, double c2) -> int {
+    if (!dg_fused) return smoother_step(c, l, x64, dt, c1, c2, s);
+    HIP_TRY(launch_sipg_cheb(c, L, cur, L.b, L.d, other, x64, dt, c1, c2, s));
+    std::swap(cur, other);
+    return MFL_OK;
+  };
   if (zero_start) {
     if (gll_jacobi(c))
       HIP_TRY(launch_dg_gll_cheb_first(c, L, b_in, b_dtype, b_in == L.b ? nullptr : L.b, L.d, L.x, dt,
@@ -398,17 +411,16 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
                                 1.0 / theta, s));
     if (updates == 1 && last_writes) HIP_TRY(launch_cast(L.x, dt, x64_out, MFL_F64, N, s));
   } else {
-    if ((rc = smoother_step(c, l, (updates == 1) ? x64_out : nullptr, dt, 0.0, 1.0 / theta, s))) return rc;
+    if ((rc = step((updates == 1) ? x64_out : nullptr, 0.0, 1.0 / theta))) return rc;
   }
   done = 1;
   double rho = delta > 0.0 ? delta / theta : 0.0;   // 1 / sigma_1
   for (; done < updates; ++done) {
     const double rho_new = 1.0 / (2.0 * theta / delta - rho);
-    if ((rc = smoother_step(c, l, done + 1 == updates ? x64_out : nullptr, dt, rho_new * rho,
-                            2.0 * rho_new / delta, s)))
-      return rc;
+    if ((rc = step(done + 1 == updates ? x64_out : nullptr, rho_new * rho, 2.0 * rho_new / delta))) return rc;
     rho = rho_new;
   }
+  if (cur != L.x) HIP_TRY(launch_cast(cur, dt, L.x, dt, N, s));
   return MFL_OK;
 }
 

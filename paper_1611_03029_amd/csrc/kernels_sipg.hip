@@ -554,6 +554,150 @@ dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const 
   }
 }
 
+// One Chebyshev update of the SIPG smoother fused with the operator application:
+//   w = b - A x,  d = c1 d + c2 C w,  x_out = x + d  (x64 = x_out when given),
+// with the point Jacobi step of the GLL-Lagrange basis C = T D'^{-1} T^T (T = S (x) S (x) S,
+// applied here along x, y, z and back, which the Kronecker form allows).  A x of a cell is
+// complete after the three phases of sipg_kernel (no halo), so the cell continues with the
+// five phases of the Jacobi step without writing A x out: per DoF x, b, D'^{-1} and d are
+// read and d and x_out written (the separate kernels also write and read A x).  x_out must
+// not alias x: neighbouring cells read x.  Lane layout and cell order of sipg_kernel.
+template <int K, typename T>
+__global__ void __launch_bounds__(kBlock)
+sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__restrict__ dpinv,
+                 T *__restrict__ d, T *__restrict__ x_out, double *__restrict__ x64, int Nc, T h, T sigma,
+                 int dmask, T c1, T c2) {
+  constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = DGLanes<K>::cpb;
+  constexpr bool WL = DGLanes<K>::wave;
+  constexpr const ct::DGTab<n, T> &tb = ct::DGTables<n, T>::tab;
+  constexpr const EOTab<n, T> &eo = ct::Tables<n, T>::eo;
+  __shared__ T U[CPB * n3], R[CPB * n3];
+  const LaneMap<n2, WL> lm(threadIdx.x, CPB);
+  const int lc = lm.slot, p = lm.p, i0 = p % n, i1 = p / n;
+  const bool inblk = lm.used;
+  int cx = 0, cy = 0, cz = 0;
+  const bool active = inblk && ColumnOrder::cell(blockIdx.x % 8, (blockIdx.x / 8) * CPB + lc, Nc, cx, cy, cz);
+  const int64_t cell = active ? cx + int64_t(Nc) * (cy + int64_t(Nc) * cz) : 0;
+  const T inv_h = T(1) / h;
+  const T scale = h * h * tb.w[i0] * tb.w[i1];
+  const int slot = inblk ? lc : 0;
+  T *Uc = U + slot * n3, *Rc = R + slot * n3;
+  const T *uc = src + cell * n3;
+  const int64_t plane = int64_t(Nc) * Nc;
+  const int64_t xl0 = cell * n3 + i1 * n2 + i0 * n;   // the lane's x-line (y = i0, z = i1)
+  // Loads are unconditional (see sipg_kernel).
+  T v[n];   // the cell's values on the lane's x-line, kept for the final update
+
+  // operator, phase z
+  if (inblk) {
+    T u[n], ul[n], ur[n], out[n];
+    const bool hasL = cz > 0, hasR = cz < Nc - 1;
+    const T *pl = src + (hasL ? cell - plane : cell) * n3, *pr = src + (hasR ? cell + plane : cell) * n3;
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      u[l] = uc[l * n2 + p];
+      ul[l] = pl[l * n2 + p];
+      ur[l] = pr[l * n2 + p];
+    }
+    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      Uc[l * n2 + p] = u[l];
+      Rc[l * n2 + p] = out[l];
+    }
+  }
+  cell_sync<WL>();
+  // operator, phase y
+  if (inblk) {
+    T u[n], ul[n], ur[n], out[n];
+    const bool hasL = cy > 0, hasR = cy < Nc - 1;
+    const T *pl = src + (hasL ? cell - Nc : cell) * n3, *pr = src + (hasR ? cell + Nc : cell) * n3;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      const int o = i1 * n2 + j * n + i0;
+      u[j] = Uc[o];
+      ul[j] = pl[o];
+      ur[j] = pr[o];
+    }
+    sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
+#pragma unroll
+    for (int j = 0; j < n; ++j) Rc[i1 * n2 + j * n + i0] += out[j];
+  }
+  cell_sync<WL>();
+  // operator, phase x, then w = b - A x and S^T along x
+  if (inblk) {
+    T ul[n], ur[n], out[n], w[n], r[n];
+    const bool hasL = cx > 0, hasR = cx < Nc - 1;
+    const T *pl = src + (hasL ? cell - 1 : cell) * n3, *pr = src + (hasR ? cell + 1 : cell) * n3;
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      const int o = i1 * n2 + i0 * n + a;
+      v[a] = Uc[o];
+      ul[a] = pl[o];
+      ur[a] = pr[o];
+      w[a] = b[xl0 + a];
+    }
+    sipg_line<n, T>(tb, v, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
+#pragma unroll
+    for (int a = 0; a < n; ++a) w[a] -= Rc[i1 * n2 + i0 * n + a] + out[a];
+    eo_apply_t<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int a = 0; a < n; ++a) Uc[i1 * n2 + i0 * n + a] = r[a];
+  }
+  cell_sync<WL>();
+  // S^T along y
+  if (inblk) {
+    T w[n], r[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) w[j] = Uc[i1 * n2 + j * n + i0];
+    eo_apply_t<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int j = 0; j < n; ++j) Rc[i1 * n2 + j * n + i0] = r[j];
+  }
+  cell_sync<WL>();
+  // S^T along z, D'^{-1}, S along z
+  if (inblk) {
+    T w[n], r[n], dp[n];
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      w[l] = Rc[l * n2 + p];
+      dp[l] = dpinv[cell * n3 + l * n2 + p];
+    }
+    eo_apply_t<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int l = 0; l < n; ++l) r[l] *= dp[l];
+    eo_apply<n, 1>(eo.S, r, w);
+#pragma unroll
+    for (int l = 0; l < n; ++l) Uc[l * n2 + p] = w[l];
+  }
+  cell_sync<WL>();
+  // S along y
+  if (inblk) {
+    T w[n], r[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) w[j] = Uc[i1 * n2 + j * n + i0];
+    eo_apply<n, 1>(eo.S, w, r);
+#pragma unroll
+    for (int j = 0; j < n; ++j) Rc[i1 * n2 + j * n + i0] = r[j];
+  }
+  cell_sync<WL>();
+  // S along x and the update of the lane's x-line
+  if (active) {
+    T w[n], cw[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) w[a] = Rc[i1 * n2 + i0 * n + a];
+    eo_apply<n, 1>(eo.S, w, cw);
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      const T dn = c1 * d[xl0 + a] + c2 * cw[a];
+      const T xn = v[a] + dn;
+      d[xl0 + a] = dn;
+      x_out[xl0 + a] = xn;
+      if (x64) x64[xl0 + a] = double(xn);
+    }
+  }
+}
+
 inline int grid_for(int64_t items, int cap = 16384) {
   int64_t g = (items + kBlock - 1) / kBlock;
   return int(g < 1 ? 1 : (g > cap ? cap : g));
@@ -682,6 +826,31 @@ hipError_t launch_dg_gll_cheb_step(const Context &c, const Level &L, const void 
 #undef CASE
   } else {
 #define CASE(K) return dg_gll_k<K, float, float, 1>(L, b, nullptr, ax, L.dinv32, d, x, x64_out, c1, c2, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int K, typename T>
+static hipError_t sipg_cheb_k(const Context &c, const Level &L, const T *x, const T *b, const T *dpinv, T *d,
+                              T *x_out, double *x64, double c1, double c2, hipStream_t s) {
+  constexpr int CPB = DGLanes<K>::cpb;
+  const int grid = 8 * ColumnOrder::blocks_per_xcd(L.Nc, CPB);
+  const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
+  sipg_cheb_kernel<K, T><<<grid, kBlock, 0, s>>>(x, b, dpinv, d, x_out, x64, L.Nc, T(L.h), T(sigma),
+                                                 dirichlet_mask(c.p), T(c1), T(c2));
+  return hipGetLastError();
+}
+
+hipError_t launch_sipg_cheb(const Context &c, const Level &L, const void *x, const void *b, void *d, void *x_out,
+                            double *x64_out, int dtype, double c1, double c2, hipStream_t s) {
+  if (dtype == MFL_F64) {
+#define CASE(K) return sipg_cheb_k<K, double>(c, L, (const double *)x, (const double *)b, L.dinv64, (double *)d, (double *)x_out, x64_out, c1, c2, s)
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else {
+#define CASE(K) return sipg_cheb_k<K, float>(c, L, (const float *)x, (const float *)b, L.dinv32, (float *)d, (float *)x_out, x64_out, c1, c2, s)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }

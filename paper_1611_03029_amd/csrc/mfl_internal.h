@@ -101,6 +101,7 @@ struct Level {
   void *halo = nullptr;         // CG apply: upper-face values of every brick (FP64 size)
   // multigrid vectors in the cycle's precision (FP64 on the coarsest level)
   void *b = nullptr, *x = nullptr, *ax = nullptr, *d = nullptr;
+  void *x2 = nullptr;           // SIPG with the GLL Jacobi smoother: the fused step's second x
   bool mg_f32 = false;          // vectors of this level are float
   double lambda_max = 0.0;
   double coarse_lmin = 0.0, coarse_lmax = 0.0;
@@ -185,6 +186,10 @@ hipError_t launch_sipg_gll_jacobi_diag(const Context &c, const Level &L, hipStre
 hipError_t launch_dg_gll_cheb_first(const Context &c, const Level &L, const void *b_in, int in_dtype,
                                     void *b_store, void *d, void *x, int dtype, double inv_theta,
                                     hipStream_t s);
+// One Chebyshev update of the SIPG smoother with the operator application fused in:
+// d = c1 d + c2 C (b - A x), x_out = x + d (x_out must not alias x).
+hipError_t launch_sipg_cheb(const Context &c, const Level &L, const void *x, const void *b, void *d, void *x_out,
+                            double *x64_out, int dtype, double c1, double c2, hipStream_t s);
 hipError_t launch_dg_gll_cheb_step(const Context &c, const Level &L, const void *b, const void *ax, void *d,
                                    void *x, double *x64_out, int dtype, double c1, double c2, hipStream_t s);
 hipError_t launch_dg_gll_jacobi(const Context &c, const Level &L, const double *r, double *z, hipStream_t s);
