@@ -27,6 +27,7 @@ Also reported, outside the timed region:
                 sample of rows of the timed workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve-degrees 2,3,4,5,6]
+       python bench.py --sipg-only [--steps K]     (the SIPG applies alone, for profiling)
 """
 import argparse
 import hashlib
@@ -301,6 +302,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed step and FP32 apply")
+    ap.add_argument("--sipg-only", action="store_true",
+                    help="only the SIPG applies (a profiling target; prints their JSON, not the bench line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path is single-GPU (multi-GPU sharding is a "
@@ -312,6 +315,9 @@ def main():
     from seeded_inputs import SEED_CG_Q4_CURVED, uniform_vector
 
     torch.cuda.set_device(0)
+    if args.sipg_only:
+        print(json.dumps({"sipg": sipg_configs(args.steps)}), flush=True)
+        return
     k, Nc = 4, 64
     prob = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1)
     n, cells, q = prob.n_dofs, prob.n_cells, (k + 1) ** 3

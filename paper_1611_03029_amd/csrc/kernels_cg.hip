@@ -516,23 +516,25 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
     return;
   }
   // Boundary brick: items outside the mesh are skipped and Dirichlet DoFs take the value of
-  // src.  The src values are loaded for all items first (from DoF 0 for items outside the
-  // mesh), so that the stores do not wait one by one.
+  // src.  Those src values are loaded first, in loops without stores, so that the stores do
+  // not wait one by one.
   T so[ITO], sh[ITH];
 #pragma unroll
   for (int it = 0; it < ITO; ++it) {
     const int i = t + it * kBlock;
     const int X = i % MX, Y = (i / MX) % MY, Z = i / (MX * MY);
-    const bool in = (OWN % kBlock == 0 || i < OWN) && gx0 + X < N1 && gy0 + Y < N1 && gz0 + Z < N1;
-    so[it] = src[in ? gbase + (X + N1 * Y) + plane * Z : 0];
+    const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
+    const bool in = (OWN % kBlock == 0 || i < OWN) && gx < N1 && gy < N1 && gz < N1;
+    so[it] = (in && dirichlet_dof(gx, gy, gz, N1, bg.dmask)) ? src[gbase + (X + N1 * Y) + plane * Z] : T(0);
   }
 #pragma unroll
   for (int it = 0; it < ITH; ++it) {
     const int i = t + it * kBlock;
     int X, Y, Z;
     halo_item(i, X, Y, Z);
-    const bool in = (HS % kBlock == 0 || i < HS) && gx0 + X < N1 && gy0 + Y < N1 && gz0 + Z < N1;
-    sh[it] = src[in ? gbase + (X + N1 * Y) + plane * Z : 0];
+    const int gx = gx0 + X, gy = gy0 + Y, gz = gz0 + Z;
+    const bool in = (HS % kBlock == 0 || i < HS) && gx < N1 && gy < N1 && gz < N1;
+    sh[it] = (in && dirichlet_dof(gx, gy, gz, N1, bg.dmask)) ? src[gbase + (X + N1 * Y) + plane * Z] : T(0);
   }
 #pragma unroll
   for (int it = 0; it < ITO; ++it) {
