@@ -20,6 +20,7 @@
 // clearing pass.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "ct_tables.h"
 #include "device_common.h"
@@ -52,20 +53,30 @@ template <> struct Brick<6> { static constexpr int x = 2, y = 2, z = 1, chunks =
 template <> struct Brick<7> { static constexpr int x = 2, y = 2, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = true; };
 template <> struct Brick<8> { static constexpr int x = 3, y = 1, z = 1, chunks = 2, ny = 1, nz = 1; static constexpr bool wave = false; };
 
-// Brick shape of the operator kernel for degree K, precision T and geometry: Brick<K> unless a
-// specialization below was measured faster.  On Cartesian cells (no metric stream) the
-// operator costs little per DoF and the halo of the brick faces takes a large share at low
-// degree; bricks that also span two chunks in y (and z) cut it (measured on 64^3 cells,
-// operator plus halo addition: Q2 -18% / -20% (FP64 / FP32), Q3 -9% / -3%, Q5 and Q6 FP64
-// -10% and -7%; the same shapes were slower for Q4 and for FP32 at Q5 and Q6).
+// Taller brick shapes for degree K, precision T and geometry where they were measured faster
+// on large meshes.  On Cartesian cells (no metric stream) the operator costs little per DoF
+// and the halo of the brick faces takes a large share at low degree; bricks that also span
+// two chunks in y (and z) cut it (measured on 64^3 cells, operator plus halo addition: Q2
+// -18% / -20% (FP64 / FP32), Q3 -9% / -3%, Q5 and Q6 FP64 -10% and -7%; slower for Q4 and
+// for FP32 at Q5 and Q6).  They give a mesh fewer work-groups, so a level uses them only
+// when at least kTallMinBricks of them fill it (coarse multigrid levels keep Brick<K>).
 template <int K, typename T, bool CURVED>
-struct BrickShape : Brick<K> {};
-template <> struct BrickShape<2, float, false> : Brick<2> { static constexpr int chunks = 4, ny = 2, nz = 2; };
-template <> struct BrickShape<2, double, false> : Brick<2> { static constexpr int chunks = 2, ny = 2, nz = 2; };
-template <> struct BrickShape<3, float, false> : Brick<3> { static constexpr int chunks = 2, ny = 2, nz = 1; };
-template <> struct BrickShape<3, double, false> : Brick<3> { static constexpr int chunks = 2, ny = 2, nz = 1; };
-template <> struct BrickShape<5, double, false> : Brick<5> { static constexpr int chunks = 2, ny = 2, nz = 1; };
-template <> struct BrickShape<6, double, false> : Brick<6> { static constexpr int chunks = 2, ny = 2, nz = 1; };
+struct TallShape : Brick<K> {
+  static constexpr bool tall = false;
+};
+template <> struct TallShape<2, float, false> : Brick<2> { static constexpr int chunks = 4, ny = 2, nz = 2; static constexpr bool tall = true; };
+template <> struct TallShape<2, double, false> : Brick<2> { static constexpr int chunks = 2, ny = 2, nz = 2; static constexpr bool tall = true; };
+template <> struct TallShape<3, float, false> : Brick<3> { static constexpr int chunks = 2, ny = 2, nz = 1; static constexpr bool tall = true; };
+template <> struct TallShape<3, double, false> : Brick<3> { static constexpr int chunks = 2, ny = 2, nz = 1; static constexpr bool tall = true; };
+template <> struct TallShape<5, double, false> : Brick<5> { static constexpr int chunks = 2, ny = 2, nz = 1; static constexpr bool tall = true; };
+template <> struct TallShape<6, double, false> : Brick<6> { static constexpr int chunks = 2, ny = 2, nz = 1; static constexpr bool tall = true; };
+#ifndef MFL_TALL_MIN_BRICKS
+#define MFL_TALL_MIN_BRICKS 512
+#endif
+constexpr int kTallMinBricks = MFL_TALL_MIN_BRICKS;
+
+template <int K, typename T, bool CURVED, bool TALL>
+using ShapeOf = typename std::conditional<TALL, TallShape<K, T, CURVED>, Brick<K>>::type;
 
 struct CellCtx {
   int i0, i1;        // lane coordinates within the cell
@@ -369,13 +380,13 @@ __device__ __forceinline__ int halo_index(int X, int Y, int Z, int MX, int MY, i
 // brick (x fastest, then y, then z; chunks outside the mesh are skipped); every lane holds
 // the src line (and, on curved meshes, the metric and kappa) of its cell of the next chunk
 // in registers, loaded while the current chunk is computed.
-template <int K, typename T, bool CURVED>
+template <int K, typename T, bool CURVED, bool TALL>
 __global__ void __launch_bounds__(kBlock)
 apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ halo,
                    const T *__restrict__ kappa, const T *__restrict__ metric, BrickGrid bg, T h) {
   constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
   using S = Shape<K>;
-  using Bk = BrickShape<K, T, CURVED>;
+  using Bk = ShapeOf<K, T, CURVED, TALL>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
   constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ;
   constexpr int NCX = Bk::chunks, NCY = Bk::ny, NCZ = Bk::nz, NCH = NCX * NCY * NCZ;
@@ -762,9 +773,9 @@ inline int grid_for(int64_t items, int cap = 65536) {
 // Bricks: chunk shape from Brick<K>; the x extent is a multiple of the chunk width chosen so
 // that there are about MFL_TARGET_BRICKS bricks (enough work-groups to fill the chip) when
 // the mesh allows, which keeps the strided x-face halos to a few planes.
-template <int K, typename T, bool CURVED>
+template <int K, typename T, bool CURVED, bool TALL>
 BrickGrid brick_grid(int Nc, int N1, int dmask) {
-  using Bk = BrickShape<K, T, CURVED>;
+  using Bk = ShapeOf<K, T, CURVED, TALL>;
   BrickGrid bg;
   bg.Nc = Nc;
   bg.N1 = N1;
@@ -778,9 +789,27 @@ BrickGrid brick_grid(int Nc, int N1, int dmask) {
   return bg;
 }
 
+// The tall shape when it exists and still gives the mesh kTallMinBricks work-groups.
+template <int K, typename T, bool CURVED>
+bool use_tall(int Nc) {
+  if constexpr (!TallShape<K, T, CURVED>::tall) {
+    return false;
+  } else {
+    const BrickGrid bg = brick_grid<K, T, CURVED, true>(Nc, K * Nc + 1, 0);
+    return int64_t(bg.nbx) * bg.nby * bg.nbz >= kTallMinBricks;
+  }
+}
+
+// The brick grid of a level (shape chosen by use_tall).
+template <int K, typename T, bool CURVED>
+BrickGrid level_grid(int Nc, int N1, int dmask) {
+  return use_tall<K, T, CURVED>(Nc) ? brick_grid<K, T, CURVED, true>(Nc, N1, dmask)
+                                    : brick_grid<K, T, CURVED, false>(Nc, N1, dmask);
+}
+
 template <int K, typename T, bool CURVED>
 int64_t halo_elements(int Nc) {
-  const BrickGrid bg = brick_grid<K, T, CURVED>(Nc, K * Nc + 1, 3);
+  const BrickGrid bg = level_grid<K, T, CURVED>(Nc, K * Nc + 1, 3);
   return int64_t(bg.nbx) * bg.nby * bg.nbz * halo_size(bg.sx * K, bg.my, bg.mz);
 }
 
@@ -821,11 +850,16 @@ static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, 
   const int dm = dmask < 0 ? dirichlet_mask(c.p) : dmask;
   (void)tab;
   if (c.p.geometry == MFL_GEOM_CURVED) {
-    const BrickGrid bg = brick_grid<K, T, true>(L.Nc, L.N1, dm);
-    apply_brick_kernel<K, T, true><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
+    const BrickGrid bg = brick_grid<K, T, true, false>(L.Nc, L.N1, dm);
+    apply_brick_kernel<K, T, true, false><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
+  } else if (use_tall<K, T, false>(L.Nc)) {
+    if constexpr (TallShape<K, T, false>::tall) {
+      const BrickGrid bg = brick_grid<K, T, false, true>(L.Nc, L.N1, dm);
+      apply_brick_kernel<K, T, false, true><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+    }
   } else {
-    const BrickGrid bg = brick_grid<K, T, false>(L.Nc, L.N1, dm);
-    apply_brick_kernel<K, T, false><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+    const BrickGrid bg = brick_grid<K, T, false, false>(L.Nc, L.N1, dm);
+    apply_brick_kernel<K, T, false, false><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
   }
   return hipGetLastError();
 }
@@ -834,8 +868,8 @@ template <int K, typename T>
 static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *halo, hipStream_t s,
                             int dmask) {
   const int dm = dmask < 0 ? dirichlet_mask(c.p) : dmask;
-  const BrickGrid bg = c.p.geometry == MFL_GEOM_CURVED ? brick_grid<K, T, true>(L.Nc, L.N1, dm)
-                                                       : brick_grid<K, T, false>(L.Nc, L.N1, dm);
+  const BrickGrid bg = c.p.geometry == MFL_GEOM_CURVED ? level_grid<K, T, true>(L.Nc, L.N1, dm)
+                                                       : level_grid<K, T, false>(L.Nc, L.N1, dm);
   const int64_t total = int64_t(bg.nbx - 1 + bg.nby - 1 + bg.nbz - 1) * L.N1 * L.N1;
   if (total == 0) return hipSuccess;
   if (total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit face index space
@@ -847,8 +881,8 @@ template <int K, typename T>
 static hipError_t cg_cheb_halo_k(const Context &c, const Level &L, const T *b, const T *ax, const T *dinv,
                                  T *d, T *x, double *x64, double c1, double c2, hipStream_t s) {
   const int dm = dirichlet_mask(c.p);
-  const BrickGrid bg = c.p.geometry == MFL_GEOM_CURVED ? brick_grid<K, T, true>(L.Nc, L.N1, dm)
-                                                       : brick_grid<K, T, false>(L.Nc, L.N1, dm);
+  const BrickGrid bg = c.p.geometry == MFL_GEOM_CURVED ? level_grid<K, T, true>(L.Nc, L.N1, dm)
+                                                       : level_grid<K, T, false>(L.Nc, L.N1, dm);
   if (L.ndofs >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit DoF index space
   const DofDiv dv{FastDiv(uint32_t(L.N1)), FastDiv(uint32_t(bg.sx * K)), FastDiv(uint32_t(bg.my)),
                   FastDiv(uint32_t(bg.mz))};

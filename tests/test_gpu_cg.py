@@ -77,6 +77,30 @@ def test_apply_cartesian_multi_brick(k, Nc, bc):
     assert rel_err(prob.apply(t(u, torch.float32)).double(), ref) <= 2e-5
 
 
+@pytest.mark.parametrize("k,Nc,nrows", [(2, 64, 600), (3, 64, 600), (5, 32, 150)])
+def test_apply_cartesian_tall_bricks_sampled(k, Nc, nrows):
+    """Meshes large enough for the taller Cartesian brick shapes (a level uses them only when
+    they give at least 512 bricks): sampled rows against the oracle's element-by-element rows,
+    concentrated on DoF planes at multiples of 6, 12 and 24 intervals (the brick faces, edges
+    and corners of those shapes), FP64 and FP32, mixed boundary conditions.  (Q6 uses the
+    chunk pattern of Q5; its oracle rows take minutes.)"""
+    box = Box(Nc, k)
+    N1 = k * Nc + 1
+    rng = np.random.default_rng(70 + k)
+    marks = sorted({c for m in (6, 12, 24) for j in (1, 2, 3) for c in (m * j - 1, m * j, m * j + 1)
+                    if 0 <= c < N1} | {0, 1, N1 - 2, N1 - 1})
+    g = rng.choice(marks, size=(2 * nrows // 3, 3))
+    rows = np.unique(np.concatenate([g[:, 0] + N1 * (g[:, 1] + N1 * g[:, 2]),
+                                     rng.integers(0, box.n_dofs, nrows // 3)]))
+    u = uniform_vector(box.n_dofs, 80 + k)
+    ref = o_cg.apply_rows(box, u, rows, bc="mixed")
+    prob = mfl.Problem(k, Nc, bc=mfl.MIXED)
+    y = prob.apply(t(u)).cpu().numpy()[rows]
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    y32 = prob.apply(t(u, torch.float32)).double().cpu().numpy()[rows]
+    assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("geom", [0.0, 0.1])
 def test_neumann_apply_and_null_space(geom):
     k, Nc = 3, 3
