@@ -150,7 +150,8 @@ struct NoOp {
 //   A_e = scale (K (x) M (x) M + M (x) K (x) M + M (x) M (x) K),  scale = kappa_e h,
 // of the reference 1D mass M and stiffness K of the GLL basis (the same numbers as the
 // quadrature form, re-associated).  Seven 1D applications per line set.
-// u: the lane's gathered z-line.  Buffers A..D: n^3 each.  TXS == 0: y_e ends in A;
+// u: the lane's gathered z-line.  Buffers A..D: n^3 each; C and D may alias A and B (every
+// phase reads only the lines its lane then rewrites).  TXS == 0: y_e ends in A;
 // TXS > 0: y_e is added (LDS atomics) into `tile` (row stride TXS, plane stride
 // TXS * TYS, this cell's origin at `tile`).  after_gather() runs once u is consumed (it may
 // overwrite u with the next cell's line).  Contains 3 cell barriers.
@@ -395,7 +396,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
                 "chunk does not fit the work-group");
   constexpr int MX = NCX * CX * K, MY = NCY * BY * K, MZ = NCZ * BZ * K;   // brick extent in DoF intervals
   constexpr int TX = MX + 1, TY = MY + 1, TZ = MZ + 1;
-  constexpr int NBUF = CURVED ? 3 : 4;
+  constexpr int NBUF = CURVED ? 3 : 2;   // Cartesian: cart_cell runs in place in two buffers
   constexpr int ITEMS = TX * TY * TZ, ITERS = (ITEMS + kBlock - 1) / kBlock;
   __shared__ T sm[NBUF][CPB * n3];
   __shared__ double tile[ITEMS];   // FP64 accumulation also for T = float (ds_add_f32 is slow)
@@ -412,7 +413,7 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   // chunks per direction that hold cells of the mesh
   const int ncx = min(NCX, (Nc - cx0 + CX - 1) / CX), ncy = min(NCY, (Nc - cy0 + BY - 1) / BY),
             ncz = min(NCZ, (Nc - cz0 + BZ - 1) / BZ);
-  T *A = sm[0] + lc * n3, *B = sm[1] + lc * n3, *C = sm[2] + lc * n3;
+  T *A = sm[0] + lc * n3, *B = sm[1] + lc * n3, *C = sm[CURVED ? 2 : 0] + lc * n3;
 
   // the lane's cell in chunk (jx, jy, jz) (inactive for jx < 0: no chunk)
   auto cell_at = [&](int jx, int jy, int jz, CellCtx &cc, int64_t &cell) {
@@ -458,9 +459,8 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
             kap = cn.active ? kappa[celln] : T(0);
           });
     } else {
-      T *D = sm[NBUF - 1] + lc * n3;
       T kn = 0;
-      cart_cell<K, T, TX, TY, WL>(cc, u, kap * h, A, B, C, D, eo, ctile, [&] {
+      cart_cell<K, T, TX, TY, WL>(cc, u, kap * h, A, B, A, B, eo, ctile, [&] {
         gather_zline(cn, src, u);
         kn = cn.active ? kappa[celln] : T(0);
       });
@@ -710,7 +710,7 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
   constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
   using S = Shape<K>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, CPB = S::cpb;
-  constexpr int NBUF = CURVED ? 3 : 4;
+  constexpr int NBUF = CURVED ? 3 : 2;   // Cartesian: cart_cell runs in place in two buffers
   __shared__ T sm[NBUF][CPB * n3];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int t = threadIdx.x, lc = t / n2, p = t - lc * n2;
@@ -726,7 +726,7 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
   }
   const CellCtx cc = make_ctx(K, n, p, inblk, active, cx, cy, cz, N1, dmask);
   const int slot = inblk ? lc : 0;
-  T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[2] + slot * n3;
+  T *A = sm[0] + slot * n3, *B = sm[1] + slot * n3, *C = sm[CURVED ? 2 : 0] + slot * n3;
   T ul[n];
   gather_zline(cc, u, ul);
   if constexpr (CURVED) {
@@ -734,8 +734,7 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
     load_metric<n, false>(active, metric + (active ? cell : 0) * (6 * n3), p, g);
     curved_cell<K, T>(cc, ul, g, T(1), A, B, C, eo);
   } else {
-    T *D = sm[NBUF - 1] + slot * n3;
-    cart_cell<K, T>(cc, ul, active ? h : T(0), A, B, C, D, eo);
+    cart_cell<K, T>(cc, ul, active ? h : T(0), A, B, A, B, eo);
   }
   T partial = 0;
   if (active) {
