@@ -485,10 +485,14 @@ dg_gll_jacobi_kernel(const A *__restrict__ b_in, T *__restrict__ b_store, const 
       T v = 0;
       if (active) {
         v = T(b_in[gi]);
-        if (MODE == 0 && b_store) b_store[gi] = v;
         if (MODE == 1) v -= ax[gi];
       }
       w[l] = v;
+    }
+    // stored after all loads: a load after a store would wait for the store
+    if (MODE == 0 && b_store && active) {
+#pragma unroll
+      for (int l = 0; l < n; ++l) b_store[base + l * n2 + p] = w[l];
     }
     eo_apply_t<n, 1>(eo.S, w, r);
 #pragma unroll
@@ -681,15 +685,19 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
     for (int j = 0; j < n; ++j) Rc[i1 * n2 + j * n + i0] = r[j];
   }
   cell_sync<WL>();
-  // S along x and the update of the lane's x-line
+  // S along x and the update of the lane's x-line (d is read in full before any store: a
+  // load after a store of the same array would wait for that store)
   if (active) {
-    T w[n], cw[n];
+    T w[n], cw[n], dold[n];
 #pragma unroll
-    for (int a = 0; a < n; ++a) w[a] = Rc[i1 * n2 + i0 * n + a];
+    for (int a = 0; a < n; ++a) {
+      w[a] = Rc[i1 * n2 + i0 * n + a];
+      dold[a] = d[xl0 + a];
+    }
     eo_apply<n, 1>(eo.S, w, cw);
 #pragma unroll
     for (int a = 0; a < n; ++a) {
-      const T dn = c1 * d[xl0 + a] + c2 * cw[a];
+      const T dn = c1 * dold[a] + c2 * cw[a];
       const T xn = v[a] + dn;
       d[xl0 + a] = dn;
       x_out[xl0 + a] = xn;
