@@ -28,6 +28,7 @@ Also reported, outside the timed region:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve-degrees 2,3,4,5,6]
        python bench.py --sipg-only [--steps K]     (the SIPG applies alone, for profiling)
+       python bench.py --solve-only [--solve-degrees 4]   (the GMG-PCG solves alone, for profiling)
 """
 import argparse
 import hashlib
@@ -304,6 +305,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the timed step and FP32 apply")
     ap.add_argument("--sipg-only", action="store_true",
                     help="only the SIPG applies (a profiling target; prints their JSON, not the bench line)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the GMG-PCG solves of --solve-degrees (a profiling target; prints their JSON)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path is single-GPU (multi-GPU sharding is a "
@@ -317,6 +320,11 @@ def main():
     torch.cuda.set_device(0)
     if args.sipg_only:
         print(json.dumps({"sipg": sipg_configs(args.steps)}), flush=True)
+        return
+    if args.solve_only:
+        for d in [int(s) for s in args.solve_degrees.split(",") if s.strip()]:
+            print(json.dumps({"gmg_pcg": {"Q%d_64^3" % d: solve_comparison(d, 64)}}), flush=True)
+            torch.cuda.empty_cache()
         return
     k, Nc = 4, 64
     prob = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1)
