@@ -139,7 +139,9 @@ int mfl_level_info(mfl_handle h, int level, int *cells_per_dim, int64_t *n_dofs,
 /* dst = A src on `level` (-1 = finest) in precision dtype (MFL_F64: double vectors,
  * MFL_F32: float vectors with FP32 geometry factors).  Eq. (mf_eval) with sum
  * factorization; CG: identity on Dirichlet DoFs; SIPG: Sec. 2.2.  src and dst must not
- * overlap.  Asynchronous. */
+ * overlap.  SIPG with an even number of points per direction (odd k) moves each cell's
+ * lines in 16-byte accesses: src and dst must then be 16-byte aligned (MFL_EINVAL
+ * otherwise; torch allocations are).  Asynchronous. */
 int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, void *stream);
 
 /* out = diag(A) on `level` (-1 = finest), in dtype (CG: Dirichlet DoFs hold 1). */

@@ -667,6 +667,9 @@ int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, vo
   if (dtype != MFL_F64 && dtype != MFL_F32) return fail(MFL_EINVAL, "unknown dtype %d", dtype);
   if (!src || !dst) return fail(MFL_EINVAL, "src/dst is NULL");
   if (src == dst) return fail(MFL_EINVAL, "src and dst must not overlap");
+  if (h->p.disc == MFL_DISC_SIPG && (h->k + 1) % 2 == 0 &&
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+    return fail(MFL_EINVAL, "SIPG vectors with an even number of points per direction must be 16-byte aligned");
   return apply_level(*h, l, dtype, src, dst, as_stream(stream), true);
 }
 

@@ -55,3 +55,22 @@ def test_sipg_32cubed_full_size(k, seed):
     assert rel_err(y[rows], o_sipg.apply_rows(dg, u, rows)) <= 1e-12
     ref = kron_apply(dg, u)
     assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_sipg_apply_alignment(k):
+    """Odd k (even n = k+1) moves x-lines in 16-byte accesses, so src and dst must be 16-byte
+    aligned: an 8-byte offset view is rejected before any kernel runs; even k accepts it and
+    gives the same result as an aligned copy."""
+    prob = mfl.Problem(k, 3, disc=mfl.SIPG)
+    n = prob.n_dofs
+    buf = torch.tensor(uniform_vector(n + 1, 50 + k), device="cuda")
+    src = buf[1:]
+    assert src.data_ptr() % 16 == 8
+    ref = prob.apply(src.clone())
+    if k % 2:
+        with pytest.raises(mfl.MflError) as e:
+            prob.apply(src)
+        assert e.value.code == mfl._mfl.MFL_EINVAL
+    else:
+        assert torch.equal(prob.apply(src), ref)
