@@ -109,6 +109,9 @@ cheb_step_kernel(const T *__restrict__ b, const T *__restrict__ ax, const T *__r
 // fine += P coarse over one coarse cell per work-group: embedding of the coarse Q_k
 // basis at the (2k+1)^3 fine nodes, applied direction by direction.  Each fine node is
 // written by exactly one coarse cell (half-open ownership), so no atomics are needed.
+// A coarse cell covers only 2k fine DoFs of each fine row, so neighbouring cells in x share
+// the fine rows' cache lines: the blocks of one XCD take consecutive cells (xcd_block), so
+// that those lines are reused in that XCD's L2 instead of being fetched by several XCDs.
 template <int K, typename TC, typename TF>
 __global__ void __launch_bounds__(kBlock)
 prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int dmask, TransferTab tt) {
@@ -117,7 +120,7 @@ prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int d
   __shared__ double P[m * n];
   __shared__ TF b0[s0], b1[m * n * n];
   for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = xcd_block(blockIdx.x, gridDim.x);
   const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
   const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
   for (int i = threadIdx.x; i < n * n * n; i += kBlock) {
@@ -155,7 +158,8 @@ prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int d
 
 // coarse = P^T (b_f - A x_f) over one coarse cell per work-group (axf == nullptr: P^T b_f).  Fine nodes shared by
 // several coarse cells are weighted by 1/multiplicity so that the sum over cells is P^T;
-// the n^3 results are added with atomics into the zeroed coarse vector.
+// the n^3 results are added with atomics into the zeroed coarse vector.  Block order as in
+// prolongate_kernel (consecutive cells on one XCD share the fine rows' cache lines).
 template <int K, typename TF, typename TC>
 __global__ void __launch_bounds__(kBlock)
 restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__restrict__ bc, int Ncc,
@@ -164,7 +168,7 @@ restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__res
   __shared__ double P[m * n];
   __shared__ TF r[m * m * m], t1[m * m * n];
   for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = xcd_block(blockIdx.x, gridDim.x);
   const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
   const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
   for (int i = threadIdx.x; i < m * m * m; i += kBlock) {
