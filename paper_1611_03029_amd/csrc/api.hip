@@ -396,6 +396,12 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
   const bool last_writes = x64_out != nullptr;
   const bool dg_fused = gll_jacobi(c) && L.x2 != nullptr;
   void *cur = L.x, *other = L.x2;
+  // the coarse-grid solve of a small Cartesian continuous level: all updates in one launch
+  if (l == 0 && zero_start && b_dtype == MFL_F64 && dt == MFL_F64 && !dg_fused && cg_coarse_cheb_supported(c, L)) {
+    HIP_TRY(launch_cg_coarse_cheb(c, L, static_cast<const double *>(b_in), static_cast<double *>(L.x), x64_out,
+                                  updates, theta, delta, s));
+    return MFL_OK;
+  }
   auto step = [&](double *x64, double c1, double c2) -> int {
     if (!dg_fused) return smoother_step(c, l, x64, dt, c1, c2, s);
     HIP_TRY(launch_sipg_cheb(c, L, cur, L.b, L.d, other, x64, dt, c1, c2, s));

@@ -890,6 +890,152 @@ static hipError_t cg_cheb_halo_k(const Context &c, const Level &L, const T *b, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Coarse-grid solve of the multigrid (Sec. 4.1) on a small Cartesian level in one
+// work-group: all `steps` updates of the Chebyshev iteration from x = 0 over [lo, hi] of the
+// Jacobi-scaled operator (theta = (lo + hi) / 2, delta = (hi - lo) / 2), with x and A x in
+// LDS and b, D^{-1} and d in registers.  Each update applies the operator cell by cell (the
+// Kronecker-sum cell of cart_cell, added into A x with LDS atomics; identity rows on
+// Dirichlet DoFs), then d = c1 d + c2 D^{-1} (b - A x), x += d.  The coarsest level holds a
+// few hundred to a few thousand DoFs: there the operator and update kernels of every
+// update are bound by launch and memory latency, while here one launch does all updates.
+// The loop count is `steps`, the same in every thread, so every barrier is reached.
+template <int K, int NC>
+struct CoarseShape {
+  static constexpr int n = K + 1, n2 = n * n, n3 = n2 * n;
+  static constexpr int N1 = K * NC + 1, N = N1 * N1 * N1, NPT = (N + kBlock - 1) / kBlock;
+  static constexpr int CELLS = NC * NC * NC, CPP = kBlock / n2, NPASS = (CELLS + CPP - 1) / CPP;
+  static constexpr long lds = long(sizeof(double)) * (2L * N + 2L * CPP * n3);
+  static constexpr bool fits = lds <= 150L * 1024 && NPT <= 32;
+};
+
+template <int K, int NC>
+__global__ void __launch_bounds__(kBlock)
+coarse_cheb_kernel(const double *__restrict__ b, const double *__restrict__ dinv,
+                   const double *__restrict__ kappa, double *__restrict__ x_out,
+                   double *__restrict__ x64, double h, int dmask, int steps, double theta,
+                   double delta) {
+  using CS = CoarseShape<K, NC>;
+  constexpr const EOTab<K + 1, double> &eo = ct::Tables<K + 1, double>::eo;
+  constexpr int n = CS::n, n2 = CS::n2, n3 = CS::n3, N1 = CS::N1, N = CS::N, NPT = CS::NPT;
+  constexpr int CELLS = CS::CELLS, CPP = CS::CPP, NPASS = CS::NPASS;
+  __shared__ double xs[N], ax[N], buf[2][CPP * n3];
+  const int t = threadIdx.x;
+  const int slot = t / n2, p = t % n2;
+  const bool used = slot < CPP;
+  double *A = buf[0] + (used ? slot : 0) * n3, *B = buf[1] + (used ? slot : 0) * n3;
+  double bb[NPT], di[NPT], d[NPT];
+  bool dir[NPT];
+  const double inv_theta = 1.0 / theta;
+  // the thread's DoFs i = t + j kBlock: b, D^{-1}, and the first update from x = 0
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = t + j * kBlock;
+    const bool in = N % kBlock == 0 || i < N;
+    bb[j] = in ? b[i] : 0.0;
+    di[j] = in ? dinv[i] : 0.0;
+    dir[j] = in && dirichlet_dof(i % N1, (i / N1) % N1, i / (N1 * N1), N1, dmask);
+    d[j] = di[j] * bb[j] * inv_theta;
+    if (in) xs[i] = d[j];
+  }
+  __syncthreads();
+  double rho = delta > 0.0 ? delta / theta : 0.0;   // 1 / sigma_1
+  for (int st = 1; st < steps; ++st) {
+    const double rho_new = 1.0 / (2.0 * theta / delta - rho);
+    const double c1 = rho_new * rho, c2 = 2.0 * rho_new / delta;
+    rho = rho_new;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int i = t + j * kBlock;
+      if (N % kBlock == 0 || i < N) ax[i] = 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+      const int cell = pass * CPP + slot;
+      const bool active = used && cell < CELLS;
+      const int cx = active ? cell % NC : 0, cy = active ? (cell / NC) % NC : 0, cz = active ? cell / (NC * NC) : 0;
+      const CellCtx cc = make_ctx(K, n, p, used, active, cx, cy, cz, N1, dmask);
+      double u[n];
+#pragma unroll
+      for (int l = 0; l < n; ++l) u[l] = (active && !z_bnd(cc, l)) ? xs[cc.base + cc.plane * l] : 0.0;
+      const double scale = active ? kappa[cell] * h : 0.0;
+      cart_cell<K, double, 0, 0, false>(cc, u, scale, A, B, A, B, eo);
+      // y_e of the lane's x-line (y = i0, z = i1) is in A after the cell's last barrier
+      if (active) {
+        const int g0 = (cz * K + cc.i1) * N1 * N1 + (cy * K + cc.i0) * N1 + cx * K;
+#pragma unroll
+        for (int q = 0; q < n; ++q) lds_add(ax + g0 + q, A[cc.i1 * n2 + cc.i0 * n + q]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int i = t + j * kBlock;
+      if (N % kBlock == 0 || i < N) {
+        const double axv = dir[j] ? xs[i] : ax[i];
+        d[j] = c1 * d[j] + c2 * di[j] * (bb[j] - axv);
+        xs[i] += d[j];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = t + j * kBlock;
+    if (N % kBlock == 0 || i < N) {
+      x_out[i] = xs[i];
+      if (x64) x64[i] = xs[i];
+    }
+  }
+}
+
+template <int K, int NC>
+static hipError_t coarse_cheb_launch(const Context &c, const Level &L, const double *b, double *x,
+                                     double *x64_out, int steps, double theta, double delta, hipStream_t s) {
+  if constexpr (CoarseShape<K, NC>::fits) {
+    coarse_cheb_kernel<K, NC><<<1, kBlock, 0, s>>>(b, L.dinv64, L.kappa64, x, x64_out, L.h, dirichlet_mask(c.p),
+                                                   steps, theta, delta);
+    return hipGetLastError();
+  }
+  return hipErrorNotSupported;
+}
+
+template <int K>
+static bool coarse_cheb_fits(int Nc) {
+  return (Nc == 1 && CoarseShape<K, 1>::fits) || (Nc == 2 && CoarseShape<K, 2>::fits) ||
+         (Nc == 3 && CoarseShape<K, 3>::fits);
+}
+
+bool cg_coarse_cheb_supported(const Context &c, const Level &L) {
+  if (c.p.disc != MFL_DISC_CG || c.p.geometry != MFL_GEOM_CARTESIAN || L.mg_f32) return false;
+  switch (c.k) {
+    case 1: return coarse_cheb_fits<1>(L.Nc);
+    case 2: return coarse_cheb_fits<2>(L.Nc);
+    case 3: return coarse_cheb_fits<3>(L.Nc);
+    case 4: return coarse_cheb_fits<4>(L.Nc);
+    case 5: return coarse_cheb_fits<5>(L.Nc);
+    case 6: return coarse_cheb_fits<6>(L.Nc);
+    case 7: return coarse_cheb_fits<7>(L.Nc);
+    case 8: return coarse_cheb_fits<8>(L.Nc);
+    default: return false;
+  }
+}
+
+hipError_t launch_cg_coarse_cheb(const Context &c, const Level &L, const double *b, double *x, double *x64_out,
+                                 int steps, double theta, double delta, hipStream_t s) {
+  if (!cg_coarse_cheb_supported(c, L) || steps < 1) return hipErrorInvalidValue;
+#define CASE(K)                                                                         \
+  switch (L.Nc) {                                                                       \
+    case 1: return coarse_cheb_launch<K, 1>(c, L, b, x, x64_out, steps, theta, delta, s); \
+    case 2: return coarse_cheb_launch<K, 2>(c, L, b, x, x64_out, steps, theta, delta, s); \
+    default: return coarse_cheb_launch<K, 3>(c, L, b, x, x64_out, steps, theta, delta, s); \
+  }
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_cg_cheb_halo(const Context &c, const Level &L, const void *b, const void *ax,
                                const void *dinv, void *d, void *x, double *x64_out, int dtype, double c1,
                                double c2, hipStream_t s) {

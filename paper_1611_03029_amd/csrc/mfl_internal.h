@@ -208,6 +208,11 @@ hipError_t launch_cheb_step(const void *b, const void *ax, const void *dinv, voi
                             hipStream_t s);
 // The Chebyshev update fused with the halo addition of launch_cg_apply (continuous Q_k; ax
 // as left by launch_cg_apply without launch_cg_halo_add).
+// Coarse-grid Chebyshev solve from x = 0 in one launch (continuous Q_k, Cartesian, FP64
+// level with at most 3 cells per direction that fits one work-group's LDS).
+bool cg_coarse_cheb_supported(const Context &c, const Level &L);
+hipError_t launch_cg_coarse_cheb(const Context &c, const Level &L, const double *b, double *x, double *x64_out,
+                                 int steps, double theta, double delta, hipStream_t s);
 hipError_t launch_cg_cheb_halo(const Context &c, const Level &L, const void *b, const void *ax,
                                const void *dinv, void *d, void *x, double *x64_out, int dtype, double c1,
                                double c2, hipStream_t s);
