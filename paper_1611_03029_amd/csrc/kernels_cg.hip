@@ -75,8 +75,23 @@ template <> struct TallShape<6, double, false> : Brick<6> { static constexpr int
 #endif
 constexpr int kTallMinBricks = MFL_TALL_MIN_BRICKS;
 
-template <int K, typename T, bool CURVED, bool TALL>
-using ShapeOf = typename std::conditional<TALL, TallShape<K, T, CURVED>, Brick<K>>::type;
+// One-chunk bricks for coarse multigrid levels.  A work-group walks the chunks of its brick
+// one after another, so on a level with few default bricks (fewer than kShortMaxBricks
+// work-groups on 256 compute units) the chip is mostly idle and the time is the length of
+// that chain; one-chunk bricks give the level more, shorter work-groups (continuous
+// Cartesian levels; degrees whose default brick has several chunks).
+template <int K>
+struct ShortShape : Brick<K> {
+  static constexpr int chunks = 1, ny = 1, nz = 1;
+};
+constexpr int kShortMaxBricks = 256;
+
+// Brick shape S of a level: 0 Brick<K>, 1 TallShape, 2 ShortShape.
+enum { kShapeDefault = 0, kShapeTall = 1, kShapeShort = 2 };
+template <int K, typename T, bool CURVED, int S>
+using ShapeOf = typename std::conditional<
+    S == kShapeTall, TallShape<K, T, CURVED>,
+    typename std::conditional<S == kShapeShort, ShortShape<K>, Brick<K>>::type>::type;
 
 struct CellCtx {
   int i0, i1;        // lane coordinates within the cell
@@ -381,13 +396,13 @@ __device__ __forceinline__ int halo_index(int X, int Y, int Z, int MX, int MY, i
 // brick (x fastest, then y, then z; chunks outside the mesh are skipped); every lane holds
 // the src line (and, on curved meshes, the metric and kappa) of its cell of the next chunk
 // in registers, loaded while the current chunk is computed.
-template <int K, typename T, bool CURVED, bool TALL>
+template <int K, typename T, bool CURVED, int SHAPE>
 __global__ void __launch_bounds__(kBlock)
 apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ halo,
                    const T *__restrict__ kappa, const T *__restrict__ metric, BrickGrid bg, T h) {
   constexpr const EOTab<K + 1, T> &eo = ct::Tables<K + 1, T>::eo;
   using S = Shape<K>;
-  using Bk = ShapeOf<K, T, CURVED, TALL>;
+  using Bk = ShapeOf<K, T, CURVED, SHAPE>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3;
   constexpr int CX = Bk::x, BY = Bk::y, BZ = Bk::z, CPB = CX * BY * BZ;
   constexpr int NCX = Bk::chunks, NCY = Bk::ny, NCZ = Bk::nz, NCH = NCX * NCY * NCZ;
@@ -772,9 +787,9 @@ inline int grid_for(int64_t items, int cap = 65536) {
 // Bricks: chunk shape from Brick<K>; the x extent is a multiple of the chunk width chosen so
 // that there are about MFL_TARGET_BRICKS bricks (enough work-groups to fill the chip) when
 // the mesh allows, which keeps the strided x-face halos to a few planes.
-template <int K, typename T, bool CURVED, bool TALL>
+template <int K, typename T, bool CURVED, int SHAPE>
 BrickGrid brick_grid(int Nc, int N1, int dmask) {
-  using Bk = ShapeOf<K, T, CURVED, TALL>;
+  using Bk = ShapeOf<K, T, CURVED, SHAPE>;
   BrickGrid bg;
   bg.Nc = Nc;
   bg.N1 = N1;
@@ -788,22 +803,37 @@ BrickGrid brick_grid(int Nc, int N1, int dmask) {
   return bg;
 }
 
-// The tall shape when it exists and still gives the mesh kTallMinBricks work-groups.
-template <int K, typename T, bool CURVED>
-bool use_tall(int Nc) {
-  if constexpr (!TallShape<K, T, CURVED>::tall) {
-    return false;
-  } else {
-    const BrickGrid bg = brick_grid<K, T, CURVED, true>(Nc, K * Nc + 1, 0);
-    return int64_t(bg.nbx) * bg.nby * bg.nbz >= kTallMinBricks;
-  }
+template <int K, typename T, bool CURVED, int SHAPE>
+int64_t brick_count(int Nc) {
+  const BrickGrid bg = brick_grid<K, T, CURVED, SHAPE>(Nc, K * Nc + 1, 0);
+  return int64_t(bg.nbx) * bg.nby * bg.nbz;
 }
 
-// The brick grid of a level (shape chosen by use_tall).
+template <int K>
+constexpr bool kHasShort = Brick<K>::chunks > 1;
+
+// The brick shape of a level: the tall shape when it exists and still gives the mesh
+// kTallMinBricks work-groups; one-chunk bricks on continuous Cartesian levels with fewer
+// than kShortMaxBricks default bricks; Brick<K> otherwise.
+template <int K, typename T, bool CURVED>
+int level_shape(int Nc) {
+  if constexpr (TallShape<K, T, CURVED>::tall) {
+    if (brick_count<K, T, CURVED, kShapeTall>(Nc) >= kTallMinBricks) return kShapeTall;
+  }
+  if constexpr (!CURVED && kHasShort<K>) {
+    if (brick_count<K, T, CURVED, kShapeDefault>(Nc) < kShortMaxBricks) return kShapeShort;
+  }
+  return kShapeDefault;
+}
+
+// The brick grid of a level (shape chosen by level_shape).
 template <int K, typename T, bool CURVED>
 BrickGrid level_grid(int Nc, int N1, int dmask) {
-  return use_tall<K, T, CURVED>(Nc) ? brick_grid<K, T, CURVED, true>(Nc, N1, dmask)
-                                    : brick_grid<K, T, CURVED, false>(Nc, N1, dmask);
+  switch (level_shape<K, T, CURVED>(Nc)) {
+    case kShapeTall: return brick_grid<K, T, CURVED, kShapeTall>(Nc, N1, dmask);
+    case kShapeShort: return brick_grid<K, T, CURVED, kShapeShort>(Nc, N1, dmask);
+    default: return brick_grid<K, T, CURVED, kShapeDefault>(Nc, N1, dmask);
+  }
 }
 
 template <int K, typename T, bool CURVED>
@@ -849,16 +879,26 @@ static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, 
   const int dm = dmask < 0 ? dirichlet_mask(c.p) : dmask;
   (void)tab;
   if (c.p.geometry == MFL_GEOM_CURVED) {
-    const BrickGrid bg = brick_grid<K, T, true, false>(L.Nc, L.N1, dm);
-    apply_brick_kernel<K, T, true, false><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
-  } else if (use_tall<K, T, false>(L.Nc)) {
-    if constexpr (TallShape<K, T, false>::tall) {
-      const BrickGrid bg = brick_grid<K, T, false, true>(L.Nc, L.N1, dm);
-      apply_brick_kernel<K, T, false, true><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
-    }
+    const BrickGrid bg = brick_grid<K, T, true, kShapeDefault>(L.Nc, L.N1, dm);
+    apply_brick_kernel<K, T, true, kShapeDefault><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
   } else {
-    const BrickGrid bg = brick_grid<K, T, false, false>(L.Nc, L.N1, dm);
-    apply_brick_kernel<K, T, false, false><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+    const int shape = level_shape<K, T, false>(L.Nc);
+    if constexpr (TallShape<K, T, false>::tall) {
+      if (shape == kShapeTall) {
+        const BrickGrid bg = brick_grid<K, T, false, kShapeTall>(L.Nc, L.N1, dm);
+        apply_brick_kernel<K, T, false, kShapeTall><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+        return hipGetLastError();
+      }
+    }
+    if constexpr (kHasShort<K>) {
+      if (shape == kShapeShort) {
+        const BrickGrid bg = brick_grid<K, T, false, kShapeShort>(L.Nc, L.N1, dm);
+        apply_brick_kernel<K, T, false, kShapeShort><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+        return hipGetLastError();
+      }
+    }
+    const BrickGrid bg = brick_grid<K, T, false, kShapeDefault>(L.Nc, L.N1, dm);
+    apply_brick_kernel<K, T, false, kShapeDefault><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
   }
   return hipGetLastError();
 }

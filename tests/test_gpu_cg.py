@@ -101,6 +101,28 @@ def test_apply_cartesian_tall_bricks_sampled(k, Nc, nrows):
     assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("k,Nc,extents", [(3, 24, (6, 24)), (4, 32, (8, 32))])
+def test_apply_cartesian_default_bricks_sampled(k, Nc, extents):
+    """Meshes with enough default (multi-chunk) bricks that neither the tall nor the one-chunk
+    shape of small multigrid levels is used (the smaller meshes above take the one-chunk
+    bricks): sampled rows concentrated on the brick faces (DoF planes at multiples of the
+    brick extents), FP64 and FP32, mixed boundary conditions."""
+    box = Box(Nc, k)
+    N1 = k * Nc + 1
+    rng = np.random.default_rng(90 + k)
+    marks = sorted({c for m in extents for j in range(1, N1 // m + 1) for c in (m * j - 1, m * j, m * j + 1)
+                    if 0 <= c < N1} | {0, 1, N1 - 2, N1 - 1})
+    g = rng.choice(marks, size=(200, 3))
+    rows = np.unique(np.concatenate([g[:, 0] + N1 * (g[:, 1] + N1 * g[:, 2]), rng.integers(0, box.n_dofs, 100)]))
+    u = uniform_vector(box.n_dofs, 95 + k)
+    ref = o_cg.apply_rows(box, u, rows, bc="mixed")
+    prob = mfl.Problem(k, Nc, bc=mfl.MIXED)
+    y = prob.apply(t(u)).cpu().numpy()[rows]
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    y32 = prob.apply(t(u, torch.float32)).double().cpu().numpy()[rows]
+    assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("geom", [0.0, 0.1])
 def test_neumann_apply_and_null_space(geom):
     k, Nc = 3, 3
