@@ -48,6 +48,11 @@ KERNEL_SOURCES = ["paper_1611_03029_amd/csrc/kernels_cg.hip", "paper_1611_03029_
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_apply_q4_64cubed_curved_traffic.json")
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -333,6 +338,7 @@ def main():
     y64 = torch.empty_like(u64)
     ms_step, kern_ms, launches = time_applies(prob, u64, y64, args.steps, args.warmup)
     protocol = repetitions(prob, u64, y64)
+    progress("timed FP64 applies done")
     traffic = measured_traffic()
     bytes64 = apply_bytes(n, cells, q, 8)
     achieved = bytes64 / (kern_ms * 1e-3) / 1e9
@@ -377,18 +383,24 @@ def main():
         "paper_context": {"cg_curved_q4_dofs_per_s": 4.58e8,
                           "hardware": "2x14-core Xeon E5-2690 v4 (Broadwell), FP64, 393216-cell shell"},
     }
+    progress("FP32 applies done")
     if not args.no_extras:
         result["small_q2"] = small_config(args.steps)
         result["sipg"] = sipg_configs(args.steps)
+        progress("small Q2 and SIPG applies done")
         solves = {}
         for d in [int(s) for s in args.solve_degrees.split(",") if s.strip()]:
             solves["Q%d_64^3" % d] = solve_comparison(d, 64)
             torch.cuda.empty_cache()
+            progress("GMG-PCG Q%d solves done" % d)
         result["gmg_pcg"] = solves
         result["adjoint"] = adjoint_config()
+        progress("adjoint workload done")
         result["paper_example"] = paper_example()
+        progress("paper example solves done")
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        progress("CPU oracle baseline done")
     print(json.dumps(result))
 
 
