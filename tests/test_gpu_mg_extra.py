@@ -82,7 +82,7 @@ def test_sipg_multigrid_high_degree(k):
 
 @pytest.mark.parametrize("k,nc,bc", [(1, 2, "dirichlet"), (2, 2, "mixed"), (3, 1, "mixed"), (3, 2, "dirichlet"),
                                      (4, 2, "dirichlet"), (4, 3, "mixed"), (5, 2, "mixed"), (6, 2, "dirichlet"),
-                                     (7, 2, "dirichlet"), (8, 2, "dirichlet")])
+                                     (6, 3, "dirichlet"), (7, 2, "dirichlet"), (8, 2, "dirichlet")])
 def test_coarse_solve_single_level(k, nc, bc):
     """A one-level hierarchy: the V-cycle is the coarse-grid Chebyshev solve alone (Sec. 4.1),
     run on continuous Cartesian levels of up to 3^3 cells in one work-group launch, with a
