@@ -205,7 +205,7 @@ def solve_comparison(degree, cells, repeats=2):
     return out
 
 
-# The paper's solver timings for its smooth-solution example (Sec. 5, data tables of Fig.
+# The paper's solver timings for its smooth-solution example (Sec. 4.3, data tables of Fig.
 # accuracy_3d_cube: columns qTime/qIt for the matrix-free CG solver and dgTim/dgIt for
 # DG-SIP), full 28-core Broadwell node, FP64, tolerance 1e-9: {(k, Nc): (s, its, s, its)}.
 PAPER_EXAMPLE_TIMES = {(2, 64): (0.1269, 5, 1.2825, 12), (3, 64): (0.4598, 5, 2.6152, 10),

@@ -20,7 +20,7 @@
  * Gauss-Lobatto support points (Sec. 2).
  *
  * Boundary conditions: Dirichlet on all faces, Neumann on all faces (operator only), or
- * mixed as in the smooth-solution example of Sec. 5: Neumann on the faces x_e = lo and
+ * mixed as in the smooth-solution example of Sec. 4.3: Neumann on the faces x_e = lo and
  * Dirichlet on the faces x_e = lo + len.
  *
  * Vectors:
@@ -64,7 +64,7 @@ extern "C" {
 #define MFL_GEOM_CURVED 1
 #define MFL_BC_DIRICHLET 0
 #define MFL_BC_NEUMANN 1
-#define MFL_BC_MIXED 2        /* Neumann at x_e = lo, Dirichlet at x_e = lo + len (Sec. 5) */
+#define MFL_BC_MIXED 2        /* Neumann at x_e = lo, Dirichlet at x_e = lo + len (Sec. 4.3) */
 #define MFL_F64 0
 #define MFL_F32 1
 #define MFL_DG_JACOBI_GAUSS 0  /* SIPG smoother: point Jacobi of the Gauss-point basis */
@@ -171,10 +171,7 @@ int mfl_pcg_solve(mfl_handle h, const double *b, double *x, double rtol, int max
  * Dirichlet DoFs.  Asynchronous. */
 int mfl_rhs_sine(mfl_handle h, double *b, void *stream);
 
-/* Adjoint solve A lambda = dJdu with the same operator and preconditioner (A is symmetric);
- * the Dirichlet entries of the right-hand side are taken as zero.  Same outputs and errors
- * as mfl_pcg_solve. */
-/* Right-hand side of the smooth-solution example (Sec. 5, eq. pois_analytic: a sum of
+/* Right-hand side of the smooth-solution example (Sec. 4.3, eq. pois_analytic: a sum of
  * three Gaussians of width 1/5 centred at (-0.5,0.5,0.25), (-0.6,-0.5,-0.125),
  * (0.5,-0.5,0.5)) on the handle's Cartesian CG mesh and boundary conditions:
  *   b_i = int f phi_i + int_{Neumann faces} (grad u . n) phi_i - (A0 x0)_i  off the
@@ -189,6 +186,9 @@ int mfl_rhs_sine(mfl_handle h, double *b, void *stream);
  * Errors: MFL_EUNSUPPORTED for curved meshes.  Asynchronous. */
 int mfl_rhs_gaussians(mfl_handle h, double *b, void *stream);
 
+/* Adjoint solve A lambda = dJdu with the same operator and preconditioner (A is symmetric);
+ * the Dirichlet entries of the right-hand side are taken as zero.  Same outputs and errors
+ * as mfl_pcg_solve. */
 int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double rtol, int maxit,
                       int *iters, double *final_rel_res, void *stream);
 

@@ -1,4 +1,4 @@
-"""The three-dimensional example with smooth solution (Sec. 5, eq. pois_analytic).
+"""The three-dimensional example with smooth solution (Sec. 4.3, eq. pois_analytic).
 
 The analytic solution is a sum of three Gaussians of width alpha = 1/5,
 

@@ -12,7 +12,7 @@
   a zero initial guess (pre-smoothing) that costs five matrix-vector products,
   from a nonzero one (post-smoothing) six, including the initial residual.  With
   the outer product and the residual before restriction this gives the 13 fine
-  level products per iteration the paper counts (Sec. 4.6).
+  level products per iteration the paper counts (Sec. 4.3).
 * Coarse solver: Chebyshev iteration over the exact extreme eigenvalues of
   D^{-1} A of the interior block, with the number of steps from the a-priori bound
   2 ((sqrt(c)-1)/(sqrt(c)+1))^m <= 1e-3 (c = lambda_max / lambda_min).

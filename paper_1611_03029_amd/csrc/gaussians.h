@@ -7,7 +7,7 @@
 
 namespace mfl {
 
-// The solution of the smooth-solution example (Sec. 5, eq. pois_analytic): three Gaussians
+// The solution of the smooth-solution example (Sec. 4.3, eq. pois_analytic): three Gaussians
 // of width alpha = 1/5, u = (alpha sqrt(2 pi))^-3 sum_j exp(-|x - x_j|^2 / alpha^2).
 // Returns u, grad u and Laplace u (in 3D, Laplace exp(-r^2/a^2) = (4 r^2/a^4 - 6/a^2) exp).
 __device__ inline void gaussians(const double x[3], double &u, double g[3], double &lap) {

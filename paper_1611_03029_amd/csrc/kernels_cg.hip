@@ -16,8 +16,10 @@
 // owning the domain's upper plane).  After its cells the work-group stores the owned DoFs
 // of the tile (Dirichlet DoFs get the identity-row value src) and writes the tile's upper
 // faces, which belong to neighbouring bricks, to the brick's halo record.  A second
-// kernel adds the halo records into the lower faces of each brick.  Deterministic; no
-// clearing pass.
+// kernel adds the halo records into the lower faces of each brick.  No global atomics and
+// no clearing pass.  A DoF shared by cells of one brick sums their contributions with LDS
+// atomics in whatever order the wavefronts reach them, so results agree between runs to
+// rounding, not bitwise.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>

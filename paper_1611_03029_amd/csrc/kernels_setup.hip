@@ -1,6 +1,6 @@
 // Setup kernels of the continuous Q_k operator (FP64): per-quadrature-point metric of
 // curved cells, the matrix diagonal for the Jacobi smoother, and the right-hand sides of
-// the sine problem and of the three-Gaussian example (Sec. 5, eq. pois_analytic).
+// the sine problem and of the three-Gaussian example (Sec. 4.3, eq. pois_analytic).
 #include <cmath>
 
 #include "device_common.h"

@@ -8,9 +8,9 @@ The oracle cannot assemble these sizes, so the checks are properties that hold a
 - the FP32 and FP64 V-cycles give the same solution to 1e-8 (relative, max norm) with
   iteration counts within one of each other;
 - the iteration count is h-independent and in the range the paper reports for this
-  multigrid (5-6 iterations on Cartesian meshes, Sec. 4.6): 4 to 7 here;
+  multigrid (5-6 iterations on Cartesian meshes, Sec. 4.3): 4 to 7 here;
 - at Q2 the nodal error against u = sin(pi x) sin(pi y) sin(pi z) falls at least at the rate
-  k + 1 - 0.3 from 32^3 to 64^3 cells (Sec. 5 observes the optimal rate k + 1; at the GLL nodes
+  k + 1 - 0.3 from 32^3 to 64^3 cells (Sec. 4.3 observes the optimal rate k + 1; at the GLL nodes
   the oracle's direct solves show k + 2 on 4^3-16^3 cells).  From Q3 on, the nodal error on
   64^3 cells (below 1e-10 by that rate) is under what a 1e-10 residual resolves, and only a
   bound (1e-8) is checked.

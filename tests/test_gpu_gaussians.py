@@ -1,5 +1,5 @@
 """GPU parity for mixed boundary conditions on (-1,1)^3 and the smooth-solution example
-(three Gaussians, Sec. 5) against the oracle and the errors the paper prints.
+(three Gaussians, Sec. 4.3) against the oracle and the errors the paper prints.
 
 Tolerances: FP64 operator and right-hand side within 1e-12 relative (max norm) of the
 oracle; FP32 operator within 2e-5; solutions within 1e-8 of the oracle's; L2 errors of the

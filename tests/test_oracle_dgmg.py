@@ -3,7 +3,7 @@
 
 The embedding is pinned by exact reproduction of Q_k polynomials; the multigrid solution by
 the sparse direct solve; the boundary data terms by the divergence theorem, by consistency
-with a polynomial solution and by the DG-SIP errors the paper prints (Sec. 5, c_pen = 3).
+with a polynomial solution and by the DG-SIP errors the paper prints (Sec. 4.3, c_pen = 3).
 """
 import os
 

@@ -7,7 +7,7 @@
   Chebyshev polynomial T_m((theta - mu)/delta) / T_m(theta/delta) at the
   eigenvalues mu of D^{-1}A (closed form of the Chebyshev iteration).
 * The coarse solver meets its a-priori bound 1e-3 in the energy norm.
-* 13 fine-level products per iteration (65 in 5 iterations, Section 4.6) and
+* 13 fine-level products per iteration (65 in 5 iterations, Section 4.3) and
   h-independent iteration counts near the paper's 5 (Table solver_times_3d).
 * Embedding exactness: the prolongation of a coarse Q_k interpolant of a Q_k
   function equals its fine interpolant.
