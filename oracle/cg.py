@@ -45,16 +45,18 @@ def cell_geometry(node_xyz, grad):
     return np.einsum("eia,bqi->eqab", node_xyz, grad)
 
 
-def element_matrices(box, kappa=None, cells=None, n_quad=None):
+def element_matrices(box, kappa=None, cells=None, n_quad=None, kappa_fn=None):
     """Dense element stiffness matrices (len(cells), n^3, n^3), eq. (mf_eval).
 
-    kappa: per-cell diffusion coefficient (None: 1).  n_quad: Gauss points per
-    direction (default k+1, the paper's choice).
+    kappa: per-cell diffusion coefficient (None: 1).  kappa_fn: an optional coefficient
+    of the position, evaluated at the physical image of every quadrature point and
+    multiplied into the cell's kappa (the variable-coefficient case of Sec. 4.3).
+    n_quad: Gauss points per direction (default k+1, the paper's choice).
     """
     cells = np.arange(box.n_cells) if cells is None else np.asarray(cells)
     m = box.n if n_quad is None else int(n_quad)
     xq, wq = gauss_legendre(m)
-    _, grad = reference_tables(box.gll, xq)
+    val, grad = reference_tables(box.gll, xq)
     w3 = tensor_weights(wq)
     kap = np.ones(box.n_cells) if kappa is None else np.asarray(kappa, dtype=np.float64)
     n3 = box.n ** 3
@@ -72,15 +74,17 @@ def element_matrices(box, kappa=None, cells=None, n_quad=None):
         # physical gradients J^{-T} grad_xi phi_i: g[e,q,i,a] = sum_b Jinv[e,q,b,a] grad[b,q,i]
         g = np.einsum("eqba,bqi->eqia", Jinv, grad)
         wdet = w3[None, :] * det * kap[cs][:, None]
+        if kappa_fn is not None:
+            wdet = wdet * kappa_fn(np.einsum("qi,eia->eqa", val, X))
         out[s:s + len(cs)] = np.einsum("eq,eqia,eqja->eij", wdet, g, g)
     return out
 
 
-def assemble(box, kappa=None, bc="dirichlet", n_quad=None):
+def assemble(box, kappa=None, bc="dirichlet", n_quad=None, kappa_fn=None):
     """Global CSR matrix.  Identity rows/columns on the DoFs of the Dirichlet faces of
     `bc` ('dirichlet': all faces, 'mixed': the upper faces, or a face mask); 'neumann':
     the plain assembled matrix (natural conditions everywhere)."""
-    Ae = element_matrices(box, kappa, n_quad=n_quad)
+    Ae = element_matrices(box, kappa, n_quad=n_quad, kappa_fn=kappa_fn)
     dofs = box.cell_dofs()
     n3 = box.n ** 3
     rows = np.repeat(dofs, n3, axis=1).ravel()
@@ -108,7 +112,7 @@ def cells_of_dof(box, dof):
     return [cx + Nc * (cy + Nc * cz) for cz in ranges[2] for cy in ranges[1] for cx in ranges[0]]
 
 
-def apply_rows(box, u, rows, kappa=None, bc="dirichlet"):
+def apply_rows(box, u, rows, kappa=None, bc="dirichlet", kappa_fn=None):
     """(A u)[rows] with the operator of `assemble` (same bc), element by element.
 
     Used at sizes where the CSR matrix does not fit: each requested row is the
@@ -119,7 +123,7 @@ def apply_rows(box, u, rows, kappa=None, bc="dirichlet"):
     bmask = box.boundary_mask(bc)
     cell_lists = [cells_of_dof(box, int(r)) for r in rows]
     uniq = np.unique(np.concatenate([np.asarray(c) for c in cell_lists]))
-    Ae = element_matrices(box, kappa, cells=uniq)
+    Ae = element_matrices(box, kappa, cells=uniq, kappa_fn=kappa_fn)
     dofs = box.cell_dofs(uniq)
     where = {int(c): i for i, c in enumerate(uniq)}
     uz = np.where(bmask, 0.0, u)
@@ -133,6 +137,20 @@ def apply_rows(box, u, rows, kappa=None, bc="dirichlet"):
             loc = int(np.nonzero(dofs[e] == r)[0][0])
             y[t] += Ae[e, loc] @ uz[dofs[e]]
     return y
+
+
+def cosine_coefficient(amp=1e6):
+    """The strongly varying coefficient of Sec. 4.3, eq. (diffusivity_shell), read with
+    each cosine factor squared so that it is positive (as printed, 1 + 10^6 times the
+    product of the cosines changes sign, which no diffusion coefficient may):
+        kappa(x) = 1 + amp * prod_{e=1..3} cos^2(2 pi x_e + 0.1 e).
+    Returns the function of positions x[..., 3]."""
+    def kappa(x):
+        p = np.ones(x.shape[:-1])
+        for e in range(3):
+            p = p * np.cos(2.0 * np.pi * x[..., e] + 0.1 * (e + 1)) ** 2
+        return 1.0 + amp * p
+    return kappa
 
 
 def sine_solution(x):

@@ -146,11 +146,13 @@ def coarse_steps(lmin, lmax, eps=1e-3):
 
 class Multigrid:
     """Level hierarchy, smoother data and V(1,1) cycle for the CG operator with Dirichlet
-    conditions on the faces of `bc` ('dirichlet': all, 'mixed': the upper faces)."""
+    conditions on the faces of `bc` ('dirichlet': all, 'mixed': the upper faces).  A
+    position-dependent coefficient kappa_fn is evaluated at the quadrature points of every
+    level (each level is re-discretized), on top of the cellwise kappa."""
 
     def __init__(self, fine_cells, degree, kappa=None, curve_amp=0.0, min_cells=2,
                  cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_eps=1e-3,
-                 bc="dirichlet", lo=0.0, length=1.0):
+                 bc="dirichlet", lo=0.0, length=1.0, kappa_fn=None):
         self.cheb_updates = cheb_degree + 1
         sizes = []
         Nc = fine_cells
@@ -168,7 +170,7 @@ class Multigrid:
         self.levels = []
         for l, Nc in enumerate(sizes):
             box = Box(Nc, degree, curve_amp, lo=lo, length=length)
-            A = cg.assemble(box, kappas[l], bc=bc)
+            A = cg.assemble(box, kappas[l], bc=bc, kappa_fn=kappa_fn)
             Dinv = 1.0 / A.diagonal()
             lev = {"box": box, "A": A, "Dinv": Dinv, "kappa": kappas[l]}
             if l == 0:
