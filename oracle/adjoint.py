@@ -17,9 +17,11 @@ from . import cg
 from .mesh import Box
 
 
-def gradient(box, u, lam):
-    """g_c = -lambda_c^T A_c^{(1)} u_c with boundary entries of u, lambda zeroed."""
-    Ae = cg.element_matrices(box, None)
+def gradient(box, u, lam, kappa_fn=None):
+    """g_c = -lambda_c^T A_c^{(1)} u_c with boundary entries of u, lambda zeroed.  With a
+    position-dependent factor kappa_fn of the coefficient (kappa = kappa_c kappa_fn(x)),
+    A_c^{(1)} is the element matrix at kappa_c = 1 with that factor kept."""
+    Ae = cg.element_matrices(box, None, kappa_fn=kappa_fn)
     dofs = box.cell_dofs()
     bmask = box.boundary_mask()
     uz = np.where(bmask, 0.0, u)[dofs]
@@ -27,19 +29,19 @@ def gradient(box, u, lam):
     return -np.einsum("ei,eij,ej->e", lz, Ae, uz)
 
 
-def solve_direct(box, kappa, b):
-    A = cg.assemble(box, kappa)
+def solve_direct(box, kappa, b, kappa_fn=None):
+    A = cg.assemble(box, kappa, kappa_fn=kappa_fn)
     return spla.spsolve(A.tocsc(), b), A
 
 
-def objective_and_gradient(cells_per_dim, degree, kappa, u_target, curve_amp=0.0):
+def objective_and_gradient(cells_per_dim, degree, kappa, u_target, curve_amp=0.0, kappa_fn=None):
     """J and dJ/dkappa with direct solves (the plain definition)."""
     box = Box(cells_per_dim, degree, curve_amp)
     b = cg.rhs(box)
-    u, A = solve_direct(box, kappa, b)
+    u, A = solve_direct(box, kappa, b, kappa_fn)
     res = u - u_target
     J = 0.5 * float(res @ res)
     rhs_adj = res.copy()
     rhs_adj[box.boundary_mask()] = 0.0
     lam = spla.spsolve(A.tocsc(), rhs_adj)
-    return J, gradient(box, u, lam), u, lam
+    return J, gradient(box, u, lam, kappa_fn), u, lam

@@ -42,7 +42,7 @@ def tensor_weights(w):
 
 def cell_geometry(node_xyz, grad):
     """J[e, q, a, b] = d x_a / d xi_b = sum_i x_i[a] d phi_i / d xi_b at each point."""
-    return np.einsum("eia,bqi->eqab", node_xyz, grad)
+    return np.einsum("eia,bqi->eqab", node_xyz, grad, optimize=True)
 
 
 def element_matrices(box, kappa=None, cells=None, n_quad=None, kappa_fn=None):
@@ -72,11 +72,16 @@ def element_matrices(box, kappa=None, cells=None, n_quad=None, kappa_fn=None):
             raise ValueError("inverted cell: det J <= 0")
         Jinv = np.linalg.inv(J)
         # physical gradients J^{-T} grad_xi phi_i: g[e,q,i,a] = sum_b Jinv[e,q,b,a] grad[b,q,i]
-        g = np.einsum("eqba,bqi->eqia", Jinv, grad)
+        g = np.einsum("eqba,bqi->eqia", Jinv, grad, optimize=True)
         wdet = w3[None, :] * det * kap[cs][:, None]
         if kappa_fn is not None:
             wdet = wdet * kappa_fn(np.einsum("qi,eia->eqa", val, X))
-        out[s:s + len(cs)] = np.einsum("eq,eqia,eqja->eij", wdet, g, g)
+        # A^e_ij = sum_q sum_a wdet[e,q] g[e,q,i,a] g[e,q,j,a], formed as one batched matrix
+        # product over the combined index (q, a)
+        E, Q = g.shape[0], g.shape[1]
+        left = (g * wdet[:, :, None, None]).transpose(0, 2, 1, 3).reshape(E, n3, Q * 3)
+        right = g.transpose(0, 1, 3, 2).reshape(E, Q * 3, n3)
+        out[s:s + len(cs)] = np.matmul(left, right)
     return out
 
 
