@@ -69,6 +69,8 @@ extern "C" {
 #define MFL_F32 1
 #define MFL_DG_JACOBI_GAUSS 0  /* SIPG smoother: point Jacobi of the Gauss-point basis */
 #define MFL_DG_JACOBI_GLL 1    /* ... point Jacobi of the GLL-Lagrange basis of each cell */
+#define MFL_KAPPA_CELLWISE 0   /* kappa constant in each cell (the kappa_cells array, or 1) */
+#define MFL_KAPPA_COSINE 1     /* ... times the position-dependent field of Sec. 4.3 (below) */
 
 typedef struct mfl_params {
   int degree;             /* polynomial degree k, 1..8 */
@@ -96,11 +98,22 @@ typedef struct mfl_params {
   int use_graphs;         /* 1 (default): the V-cycle is captured once as a HIP graph on an
                              internal stream and replayed on the caller's stream; 0: kernel
                              by kernel */
+  int kappa_field;        /* MFL_KAPPA_CELLWISE (default) or MFL_KAPPA_COSINE: the cellwise
+                             kappa is multiplied at every quadrature point x_q by the strongly
+                             varying coefficient of Sec. 4.3, eq. (diffusivity_shell), read
+                             with squared cosines so that it stays positive:
+                               1 + kappa_field_amp prod_{e=1..3} cos^2(2 pi x_e + 0.1 e).
+                             It is folded into the stored per-point metric, so it needs
+                             geometry = MFL_GEOM_CURVED (curve_amp = 0 gives Cartesian cells
+                             with a per-point metric) and the continuous discretization.
+                             Every multigrid level evaluates it at its own quadrature points. */
+  double kappa_field_amp; /* amplitude of that field (default 1e6, the paper's; >= 0) */
 } mfl_params;
 
 typedef struct mfl_context *mfl_handle;
 
-/* Fill *p with the defaults above (k = 2, N_c = 8, CG, Cartesian, Dirichlet, MG in FP64). */
+/* Fill *p with the defaults above (k = 2, N_c = 8, CG, Cartesian, Dirichlet, MG in FP64,
+ * cellwise kappa). */
 int mfl_default_params(mfl_params *p);
 
 /* Sizes for params p (host only, no GPU call): number of DoFs and cells of the finest
@@ -108,23 +121,30 @@ int mfl_default_params(mfl_params *p);
  * Errors: MFL_EINVAL for an unsupported or inconsistent p (k outside 1..8, N_c not
  * reducible by halving to min_level_cells when build_mg = 1, SIPG with curved
  * geometry, multigrid with Neumann conditions on every face, a curved mesh off the unit
- * cube). */
+ * cube, a coarsest multigrid level with more than 20000 unknowns, the position-dependent
+ * kappa field without curved CG geometry). */
 int mfl_query(const mfl_params *p, int64_t *n_dofs, int64_t *n_cells, int64_t *workspace_bytes);
 
 /* Build the level hierarchy in `workspace` (device memory, >= the queried size, 256-byte
  * aligned): geometry factors (Sec. 3: per-quadrature-point metric on curved meshes, one
  * scalar per cell on Cartesian ones), Jacobi diagonals, and for build_mg = 1 the
- * lambda_max estimates of every level (Sec. 4.1) and the coarse solver's eigenvalue range.
- * kappa_cells: device array of n_cells doubles (> 0), or NULL for kappa = 1.
- * Synchronizes `stream` (the eigenvalue estimates read scalars back).  On success *out is
- * a new handle.  Errors: MFL_EINVAL (params, NULL or misaligned workspace, too small
- * size), MFL_EHIP. */
+ * lambda_max estimates of every level (Sec. 4.1) and the coarse solver's eigenvalue range
+ * (the extreme eigenvalues of the Jacobi-preconditioned coarsest operator, by Lanczos with
+ * full reorthogonalization until both have converged to rounding).
+ * kappa_cells: device array of n_cells doubles, each finite and > 0 (Sec. 2), or NULL for
+ * kappa = 1.  Synchronizes `stream` (the kappa check and the eigenvalue estimates read
+ * values back).  On success *out is a new handle.  Errors: MFL_EINVAL (params, NULL or
+ * misaligned workspace, too small size, a kappa value that is not finite and positive, a
+ * curved cell whose Jacobian determinant is not positive at some quadrature point),
+ * MFL_EHIP. */
 int mfl_setup(const mfl_params *p, void *workspace, int64_t workspace_bytes,
               const double *kappa_cells, void *stream, mfl_handle *out);
 
-/* Replace the cellwise kappa (device, n_cells doubles > 0) and rebuild everything that
- * depends on it: coarse-level kappa (mean of the 8 children), diagonals, eigenvalue
- * estimates.  Synchronizes `stream`. */
+/* Replace the cellwise kappa (device, n_cells doubles, each finite and > 0) and rebuild
+ * everything that depends on it: coarse-level kappa (mean of the 8 children), diagonals,
+ * eigenvalue estimates.  Synchronizes `stream`.  Errors: MFL_EINVAL for a NULL handle or
+ * array and for a kappa value that is not finite and positive (the handle is then left
+ * unchanged), MFL_EHIP. */
 int mfl_set_kappa(mfl_handle h, const double *kappa_cells, void *stream);
 
 /* Number of levels (1 without multigrid); level 0 is the coarsest, num_levels-1 the finest. */

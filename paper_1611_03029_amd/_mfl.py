@@ -16,6 +16,7 @@ CG, SIPG = 0, 1
 CARTESIAN, CURVED = 0, 1
 DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 DG_JACOBI_GAUSS, DG_JACOBI_GLL = 0, 1
+KAPPA_CELLWISE, KAPPA_COSINE = 0, 1
 F64, F32 = 0, 1
 _DT = {F64: torch.float64, F32: torch.float32}
 
@@ -47,6 +48,8 @@ class Params(ctypes.Structure):
         ("domain_len", ctypes.c_double),
         ("dg_jacobi_basis", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("kappa_field", ctypes.c_int),
+        ("kappa_field_amp", ctypes.c_double),
     ]
 
 
@@ -110,7 +113,8 @@ def _ptr(t):
 def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.1, bc=DIRICHLET,
                 penalty_factor=1.0, build_mg=False, mg_precision=F64, min_level_cells=2,
                 cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3,
-                domain_lo=0.0, domain_len=1.0, dg_jacobi_basis=DG_JACOBI_GLL, use_graphs=True):
+                domain_lo=0.0, domain_len=1.0, dg_jacobi_basis=DG_JACOBI_GLL, use_graphs=True,
+                kappa_field=KAPPA_CELLWISE, kappa_field_amp=1e6):
     p = Params()
     _check(lib().mfl_default_params(ctypes.byref(p)))
     p.degree, p.cells_per_dim, p.min_level_cells = degree, cells_per_dim, min_level_cells
@@ -121,7 +125,24 @@ def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.
     p.domain_lo, p.domain_len = domain_lo, domain_len
     p.dg_jacobi_basis = dg_jacobi_basis
     p.use_graphs = int(bool(use_graphs))
+    p.kappa_field, p.kappa_field_amp = kappa_field, kappa_field_amp
     return p
+
+
+def check_vector(t, n, dtype, name):
+    """Raise ValueError unless t is a contiguous CUDA tensor of `dtype` with n values: the
+    library reads or writes n values of that type through the pointer."""
+    if not torch.is_tensor(t):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a CUDA tensor (got device %s)" % (name, t.device))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() != n:
+        raise ValueError("%s must hold %d values (got %d)" % (name, n, t.numel()))
+    return t
 
 
 def query(params):
@@ -198,16 +219,10 @@ class Problem:
         _check(lib().mfl_set_kappa(self.handle, _ptr(self._kappa), _stream()))
 
     def apply(self, src, dst=None, level=-1):
-        dtype = F32 if src.dtype == torch.float32 else F64
-        if src.dtype != _DT[dtype] or not src.is_contiguous() or src.device.type != "cuda":
-            raise ValueError("src must be a contiguous float64/float32 CUDA tensor")
+        dtype = F32 if torch.is_tensor(src) and src.dtype == torch.float32 else F64
         n = self._level_dofs(level)
-        if src.numel() != n:
-            raise ValueError("src has %d values, level has %d DoFs" % (src.numel(), n))
-        if dst is None:
-            dst = torch.empty_like(src)
-        elif dst.dtype != src.dtype or dst.numel() != n or not dst.is_contiguous():
-            raise ValueError("dst must match src")
+        check_vector(src, n, _DT[dtype], "src")
+        dst = torch.empty_like(src) if dst is None else check_vector(dst, n, _DT[dtype], "dst")
         _check(lib().mfl_apply(self.handle, level, dtype, _ptr(src), _ptr(dst), _stream()))
         return dst
 
@@ -219,14 +234,26 @@ class Problem:
         return out
 
     def transfer(self, level, direction, src, dst):
-        dtype = F32 if dst.dtype == torch.float32 and direction == 0 else (
-            F32 if src.dtype == torch.float32 else F64)
-        _check(lib().mfl_transfer(self.handle, level, direction, dtype, _ptr(src), _ptr(dst), _stream()))
+        """direction 0: dst (level) += P src (level - 1); 1: dst (level - 1) = P^T src (level).
+        The fine vector is in the dtype of the call (float32 or float64); the coarse vector in
+        the same dtype, except on the coarsest level, which is always float64."""
+        nl = self.num_levels
+        lev = nl - 1 if level == -1 else level
+        if not 1 <= lev < nl:
+            raise ValueError("transfer needs a level in 1..%d (got %d)" % (nl - 1, level))
+        fine, coarse = (dst, src) if direction == 0 else (src, dst)
+        if direction not in (0, 1):
+            raise ValueError("direction must be 0 (prolongate) or 1 (restrict)")
+        dtype = F32 if torch.is_tensor(fine) and fine.dtype == torch.float32 else F64
+        cdt = torch.float64 if lev - 1 == 0 else _DT[dtype]
+        check_vector(fine, self._level_dofs(lev), _DT[dtype], "fine vector")
+        check_vector(coarse, self._level_dofs(lev - 1), cdt, "coarse vector")
+        _check(lib().mfl_transfer(self.handle, lev, direction, dtype, _ptr(src), _ptr(dst), _stream()))
         return dst
 
     def vcycle(self, r, z=None):
         r = self._as_f64(r, self.n_dofs)
-        z = torch.empty_like(r) if z is None else z
+        z = torch.empty_like(r) if z is None else check_vector(z, self.n_dofs, torch.float64, "z")
         _check(lib().mfl_vcycle(self.handle, _ptr(r), _ptr(z), _stream()))
         return z
 
@@ -243,7 +270,7 @@ class Problem:
 
     def _solve(self, fn, b, rtol, maxit, x, raise_on_noconv):
         b = self._as_f64(b, self.n_dofs)
-        x = torch.empty_like(b) if x is None else x
+        x = torch.empty_like(b) if x is None else check_vector(x, self.n_dofs, torch.float64, "x")
         it, res = ctypes.c_int(), ctypes.c_double()
         rc = fn(self.handle, _ptr(b), _ptr(x), ctypes.c_double(rtol), ctypes.c_int(maxit),
                 ctypes.byref(it), ctypes.byref(res), _stream())

@@ -37,6 +37,23 @@ int fail(int code, const char *fmt, ...) {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Faces whose DoFs are identity rows of the operator: the Dirichlet faces for CG; none for
+// SIPG, which imposes Dirichlet data weakly.
+int row_mask(const mfl_params &p) { return p.disc == MFL_DISC_CG ? dirichlet_mask(p) : 0; }
+
+// Unknowns of the coarsest multigrid level: CG without the DoFs of Dirichlet faces, SIPG all.
+int64_t coarse_unknowns(const mfl_params &p) {
+  const int64_t Nc = p.min_level_cells, n = p.degree + 1;
+  if (p.disc != MFL_DISC_CG) return Nc * Nc * Nc * n * n * n;
+  const int dm = row_mask(p);
+  const int64_t m1 = p.degree * Nc + 1 - (dm & 1) - ((dm >> 1) & 1);
+  return m1 * m1 * m1;
+}
+
+// The coarse solver's eigenvalue range comes from a Lanczos process whose basis is held on
+// the host (see coarse_interval); this bounds its size.
+constexpr int kMaxCoarseUnknowns = 20000;
+
 int check_params(const mfl_params *p) {
   if (!p) return fail(MFL_EINVAL, "params is NULL");
   if (p->degree < 1 || p->degree > kMaxDegree)
@@ -59,12 +76,21 @@ int check_params(const mfl_params *p) {
     if (!(p->penalty_factor > 0.0)) return fail(MFL_EINVAL, "penalty_factor must be > 0");
   }
   if (p->geometry == MFL_GEOM_CURVED) {
-    // det J = 1 + a pi (c s s + s c s + s s c) stays positive for |a| < 1 / (pi * 3^(1/2) ...);
-    // the map is checked cell by cell at setup only through the sign of det J at the
-    // quadrature points, so keep the amplitude in the range where it cannot fold.
+    // det J of the analytic map is 1 + a pi (c s s + s c s + s s c) >= 1 - 2 pi |a| / sqrt(3)
+    // (the bracket's extremes are +-2/sqrt(3), on the diagonal), i.e. > 0.45 for |a| <= 0.15;
+    // the interpolated map's det J is also checked at every quadrature point at setup.
     if (!(std::fabs(p->curve_amp) <= 0.15)) return fail(MFL_EINVAL, "|curve_amp| must be <= 0.15");
     if (p->domain_lo != 0.0 || p->domain_len != 1.0)
       return fail(MFL_EINVAL, "the curved map is defined on the unit cube (domain_lo 0, domain_len 1)");
+  }
+  if (p->kappa_field != MFL_KAPPA_CELLWISE && p->kappa_field != MFL_KAPPA_COSINE)
+    return fail(MFL_EINVAL, "unknown kappa_field %d", p->kappa_field);
+  if (p->kappa_field == MFL_KAPPA_COSINE) {
+    if (p->disc != MFL_DISC_CG || p->geometry != MFL_GEOM_CURVED)
+      return fail(MFL_EINVAL, "the position-dependent kappa field needs the continuous discretization on "
+                              "curved geometry (it is folded into the per-point metric)");
+    if (!(p->kappa_field_amp >= 0.0 && std::isfinite(p->kappa_field_amp)))
+      return fail(MFL_EINVAL, "kappa_field_amp must be finite and >= 0");
   }
   if (p->build_mg) {
     if (p->bc == MFL_BC_NEUMANN) return fail(MFL_EINVAL, "multigrid requires Dirichlet conditions on some faces");
@@ -78,6 +104,10 @@ int check_params(const mfl_params *p) {
     if (Nc != p->min_level_cells)
       return fail(MFL_EINVAL, "cells_per_dim %d does not halve down to min_level_cells %d",
                   p->cells_per_dim, p->min_level_cells);
+    const int64_t unknowns = coarse_unknowns(*p);
+    if (unknowns > kMaxCoarseUnknowns)
+      return fail(MFL_EINVAL, "the coarsest level has %lld unknowns; the coarse solver takes at most %d "
+                              "(choose a smaller min_level_cells)", (long long)unknowns, kMaxCoarseUnknowns);
     if (p->cheb_degree < 1 || p->cheb_degree > 64) return fail(MFL_EINVAL, "cheb_degree outside 1..64");
     if (!(p->cheb_lo > 0.0 && p->cheb_hi > p->cheb_lo)) return fail(MFL_EINVAL, "need 0 < cheb_lo < cheb_hi");
     if (p->eig_iters < 1 || p->eig_iters > 1000) return fail(MFL_EINVAL, "eig_iters outside 1..1000");
@@ -147,6 +177,7 @@ int64_t layout(Context &c, char *base) {
   }
   c.partials = b.take<double>(kReduceBlocks);
   c.scalars = b.take<double>(kNumScalars);
+  c.flags = b.take<int>(kNumFlags);
   return b.off;
 }
 
@@ -248,14 +279,12 @@ hipError_t jacobi_step(const Context &c, const Level &L, const double *r, double
   return launch_jacobi(L.dinv64, r, z, L.ndofs, s);
 }
 
-// Faces whose DoFs are identity rows of the operator: the Dirichlet faces for CG; none for
-// SIPG, which imposes Dirichlet data weakly.
-int row_mask(const Context &c) { return c.p.disc == MFL_DISC_CG ? dirichlet_mask(c.p) : 0; }
+int row_mask(const Context &c) { return row_mask(c.p); }
 
 // Jacobi-preconditioned CG on level l from the SplitMix64 start vector (key = cells per
 // direction, Dirichlet entries zero); records the Lanczos tridiagonal from alpha, beta.
-int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vector<double> &diag,
-            std::vector<double> &off, hipStream_t s) {
+int lanczos(Context &c, int l, int max_iters, std::vector<double> &diag, std::vector<double> &off,
+            hipStream_t s) {
   Level &L = c.levels[l];
   const int64_t N = L.ndofs;
   double *r = c.r, *z = c.z, *p = c.pv, *q = c.q;
@@ -283,7 +312,6 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
     if (!(pq > 0.0) || !std::isfinite(pq)) break;
     alphas.push_back(c.host_scalars[kAlpha]);
     betas.push_back(c.host_scalars[kBeta]);
-    if (run_to_convergence && c.host_scalars[kRZ] <= 1e-30 * rz0) break;
   }
   const int m = int(alphas.size());
   if (m == 0) return fail(MFL_EBREAKDOWN, "eigenvalue estimate on level %d: no CG step possible", l);
@@ -293,6 +321,98 @@ int lanczos(Context &c, int l, int max_iters, bool run_to_convergence, std::vect
     diag[j] = 1.0 / alphas[j] + (j > 0 ? betas[j - 1] / alphas[j - 1] : 0.0);
     if (j + 1 < m) off[j] = std::sqrt(betas[j]) / alphas[j];
   }
+  return MFL_OK;
+}
+
+// Extreme eigenvalues of C A on the unknowns of level l, C the level's Jacobi step (the
+// interval of the coarse-grid Chebyshev solver, Sec. 4.1).  Lanczos in the inner product of
+// C (the recurrence behind preconditioned CG): q_1 = r / |r|_C from the SplitMix64 start
+// vector, then w = A p_j - alpha_j q_j - beta_{j-1} q_{j-1} with p_j = C q_j, orthogonalized
+// twice against the whole basis, q_{j+1} = w / beta_j with beta_j = (w^T C w)^{1/2}.  The
+// basis vectors live on the host; the products with A and C run on the device.  Full
+// reorthogonalization keeps the tridiagonal's extreme eigenvalues from stalling below the
+// operator's when the start vector is nearly deflated (a clustered spectrum), which plain
+// CG-Lanczos run until its residual vanishes does not.  Stops when the Krylov space is
+// invariant (beta_j <= 1e-12 lambda_max), when it spans all unknowns, or when both extreme
+// Ritz values have moved by at most 1e-15 lambda_max over the last 8 steps.
+int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax) {
+  Level &L = c.levels[l];
+  const int64_t N = L.ndofs;
+  const int64_t unknowns = l == 0 ? coarse_unknowns(c.p) : N;
+  const int max_steps = int(std::min<int64_t>(unknowns, 4000));
+  std::vector<double> Q, P, w(N), z(N), alpha, beta;
+  auto dot = [N](const double *a, const double *b) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < N; ++i) acc += a[i] * b[i];
+    return acc;
+  };
+  // z = C w on the device
+  auto precondition = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(c.r, w.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(jacobi_step(c, L, c.r, c.z, s));
+    HIP_TRY(hipMemcpyAsync(z.data(), c.z, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFL_OK;
+  };
+  HIP_TRY(launch_random_start(c.r, L, uint64_t(L.Nc), row_mask(c), s));
+  HIP_TRY(hipMemcpyAsync(w.data(), c.r, N * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int rc = precondition();
+  if (rc) return rc;
+  double b0 = dot(w.data(), z.data());
+  if (!(b0 > 0.0) || !std::isfinite(b0))
+    return fail(MFL_EBREAKDOWN, "coarse eigenvalue range on level %d: start vector has no C-norm", l);
+  b0 = std::sqrt(b0);
+  auto push = [&](double scale) {
+    Q.resize(Q.size() + N);
+    P.resize(P.size() + N);
+    double *q = Q.data() + Q.size() - N, *p = P.data() + P.size() - N;
+    for (int64_t i = 0; i < N; ++i) {
+      q[i] = w[i] / scale;
+      p[i] = z[i] / scale;
+    }
+  };
+  push(b0);
+  double last_min = 0.0, last_max = 0.0;
+  lmin = lmax = 0.0;
+  for (int j = 0; j < max_steps; ++j) {
+    const double *qj = Q.data() + int64_t(j) * N, *pj = P.data() + int64_t(j) * N;
+    HIP_TRY(hipMemcpyAsync(c.pv, pj, N * sizeof(double), hipMemcpyHostToDevice, s));
+    if ((rc = apply_level(c, l, MFL_F64, c.pv, c.q, s))) return rc;
+    HIP_TRY(hipMemcpyAsync(w.data(), c.q, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double a = dot(pj, w.data());
+    for (int64_t i = 0; i < N; ++i) w[i] -= a * qj[i];
+    if (j > 0) {
+      const double *qp = Q.data() + int64_t(j - 1) * N;
+      for (int64_t i = 0; i < N; ++i) w[i] -= beta[j - 1] * qp[i];
+    }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i <= j; ++i) {
+        const double *qi = Q.data() + int64_t(i) * N, *pi = P.data() + int64_t(i) * N;
+        const double h = dot(pi, w.data());
+        for (int64_t e = 0; e < N; ++e) w[e] -= h * qi[e];
+      }
+    alpha.push_back(a);
+    tridiag_extremes(alpha, beta, lmin, lmax);
+    if (!std::isfinite(lmin) || !std::isfinite(lmax) || !(lmax > 0.0))
+      return fail(MFL_EBREAKDOWN, "coarse eigenvalue range on level %d: Lanczos step %d is not finite", l, j);
+    if (j + 1 == max_steps) break;
+    if ((j + 1) % 8 == 0) {
+      if (j + 1 > 8 && std::fabs(lmin - last_min) <= 1e-15 * lmax && std::fabs(lmax - last_max) <= 1e-15 * lmax)
+        break;
+      last_min = lmin;
+      last_max = lmax;
+    }
+    if ((rc = precondition())) return rc;
+    const double bb = dot(w.data(), z.data());
+    if (!(bb > 0.0) || std::sqrt(bb) <= 1e-12 * lmax) break;   // invariant Krylov space
+    beta.push_back(std::sqrt(bb));
+    push(beta.back());
+  }
+  if (!(lmin > 0.0))
+    return fail(MFL_EBREAKDOWN, "coarse eigenvalue range on level %d: smallest eigenvalue %g is not positive",
+                l, lmin);
   return MFL_OK;
 }
 
@@ -330,12 +450,7 @@ int rebuild_kappa_dependent(Context &c, hipStream_t s) {
     double lmin, lmax;
     int rc;
     if (l == 0) {
-      // unknowns: CG without the Dirichlet DoFs (N1 minus the number of Dirichlet faces
-      // per direction); SIPG all DoFs
-      const int dm = row_mask(c), m1 = L.N1 - (dm & 1) - ((dm >> 1) & 1);
-      const int interior = c.p.disc == MFL_DISC_CG ? m1 * m1 * m1 : int(L.ndofs);
-      if ((rc = lanczos(c, l, interior + 50, true, a, b, s))) return rc;
-      tridiag_extremes(a, b, lmin, lmax);
+      if ((rc = coarse_interval(c, l, s, lmin, lmax))) return rc;
       L.coarse_lmin = lmin;
       L.coarse_lmax = lmax;
       const double cond = lmax / lmin;
@@ -344,7 +459,7 @@ int rebuild_kappa_dependent(Context &c, hipStream_t s) {
                                    : int(std::ceil(std::log(2.0 / c.p.coarse_tol) / std::log(1.0 / rate)));
       if (L.coarse_steps < 1) L.coarse_steps = 1;
     } else {
-      if ((rc = lanczos(c, l, c.p.eig_iters, false, a, b, s))) return rc;
+      if ((rc = lanczos(c, l, c.p.eig_iters, a, b, s))) return rc;
       tridiag_extremes(a, b, lmin, lmax);
       L.lambda_max = lmax;
     }
@@ -545,6 +660,17 @@ int pcg(Context &c, const double *b, double *x, double rtol, int maxit, int *ite
 
 bool need_mg(const Context &c) { return c.p.build_mg != 0; }
 
+// Reads the setup error flags (synchronizes s) and turns a raised flag into MFL_EINVAL.
+int setup_flags(Context &c, hipStream_t s) {
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, c.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (f & kFlagKappa) return fail(MFL_EINVAL, "kappa holds a value that is not finite and positive");
+  if (f & kFlagDetJ)
+    return fail(MFL_EINVAL, "a curved cell has a Jacobian determinant that is not positive at a quadrature point");
+  return MFL_OK;
+}
+
 }  // namespace
 
 struct mfl_context : public Context {};
@@ -573,6 +699,8 @@ int mfl_default_params(mfl_params *p) {
   p->domain_len = 1.0;
   p->dg_jacobi_basis = MFL_DG_JACOBI_GLL;
   p->use_graphs = 1;
+  p->kappa_field = MFL_KAPPA_CELLWISE;
+  p->kappa_field_amp = 1e6;
   return MFL_OK;
 }
 
@@ -615,17 +743,21 @@ int mfl_setup(const mfl_params *p, void *workspace, int64_t workspace_bytes, con
   if (hipHostMalloc(reinterpret_cast<void **>(&c->host_scalars), kNumScalars * sizeof(double)) != hipSuccess)
     return cleanup(fail(MFL_EHIP, "hipHostMalloc of the scalar mirror failed"));
   Level &F = c->levels.back();
-  hipError_t e;
-  if (kappa_cells)
-    e = hipMemcpyAsync(F.kappa64, kappa_cells, F.ncells * sizeof(double), hipMemcpyDeviceToDevice, s);
-  else
-    e = launch_fill(F.kappa64, MFL_F64, F.ncells, 1.0, s);
+  hipError_t e = hipMemsetAsync(c->flags, 0, kNumFlags * sizeof(int), s);
+  if (e == hipSuccess) {
+    if (kappa_cells)
+      e = hipMemcpyAsync(F.kappa64, kappa_cells, F.ncells * sizeof(double), hipMemcpyDeviceToDevice, s);
+    else
+      e = launch_fill(F.kappa64, MFL_F64, F.ncells, 1.0, s);
+  }
+  if (e == hipSuccess) e = launch_check_positive(F.kappa64, F.ncells, c->flags, kFlagKappa, s);
   if (e == hipSuccess) e = launch_cast(F.kappa64, MFL_F64, F.kappa32, MFL_F32, F.ncells, s);
   if (e != hipSuccess) return cleanup(fail(MFL_EHIP, "kappa upload: %s", hipGetErrorString(e)));
   if (p->disc == MFL_DISC_CG && p->geometry == MFL_GEOM_CURVED)
     for (Level &L : c->levels)
       if ((e = launch_metric_setup(*c, L, s)) != hipSuccess)
         return cleanup(fail(MFL_EHIP, "metric setup: %s", hipGetErrorString(e)));
+  if ((rc = setup_flags(*c, s))) return cleanup(rc);
   if ((rc = rebuild_kappa_dependent(*c, s))) return cleanup(rc);
   if ((e = hipStreamSynchronize(s)) != hipSuccess)
     return cleanup(fail(MFL_EHIP, "setup: %s", hipGetErrorString(e)));
@@ -638,6 +770,9 @@ int mfl_set_kappa(mfl_handle h, const double *kappa_cells, void *stream) {
   if (!kappa_cells) return fail(MFL_EINVAL, "kappa_cells is NULL");
   hipStream_t s = as_stream(stream);
   Level &F = h->levels.back();
+  HIP_TRY(hipMemsetAsync(h->flags, 0, kNumFlags * sizeof(int), s));
+  HIP_TRY(launch_check_positive(kappa_cells, F.ncells, h->flags, kFlagKappa, s));
+  if (int rc = setup_flags(*h, s)) return rc;
   HIP_TRY(hipMemcpyAsync(F.kappa64, kappa_cells, F.ncells * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_cast(F.kappa64, MFL_F64, F.kappa32, MFL_F32, F.ncells, s));
   int rc = rebuild_kappa_dependent(*h, s);

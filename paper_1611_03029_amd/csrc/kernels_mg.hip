@@ -29,6 +29,15 @@ __global__ void __launch_bounds__(kBlock) cast_kernel(const A *s, B *d, int64_t 
   GRID_STRIDE(i, n) d[i] = B(s[i]);
 }
 
+__global__ void __launch_bounds__(kBlock) check_positive_kernel(const double *v, int64_t n, int *flag, int bit) {
+  bool bad = false;
+  GRID_STRIDE(i, n) {
+    const double x = v[i];
+    bad = bad || !(x > 0.0) || !isfinite(x);
+  }
+  if (bad) atomicOr(flag, bit);
+}
+
 __global__ void __launch_bounds__(kBlock)
 coarsen_kappa_kernel(const double *__restrict__ fine, double *__restrict__ c64, float *__restrict__ c32,
                      int Ncc) {
@@ -316,6 +325,11 @@ hipError_t launch_cast(const void *src, int sd, void *dst, int dd, int64_t n, hi
     cast_kernel<double, double><<<g, kBlock, 0, s>>>((const double *)src, (double *)dst, n);
   else
     cast_kernel<float, float><<<g, kBlock, 0, s>>>((const float *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_positive(const double *v, int64_t n, int *flag, int bit, hipStream_t s) {
+  check_positive_kernel<<<grid_for(n, 1024), kBlock, 0, s>>>(v, n, flag, bit);
   return hipGetLastError();
 }
 

@@ -13,14 +13,27 @@ namespace {
 constexpr int kBlock = 256;
 
 
+// The strongly varying coefficient of Sec. 4.3, eq. (diffusivity_shell), with each cosine
+// factor squared so that it is positive: 1 + amp prod_e cos^2(2 pi x_e + 0.1 e), e = 1..3.
+__device__ __forceinline__ double cosine_field(const double x[3], double amp) {
+  double p = 1.0;
+  for (int e = 0; e < 3; ++e) {
+    const double c = cos(2.0 * M_PI * x[e] + 0.1 * (e + 1));
+    p *= c * c;
+  }
+  return 1.0 + amp * p;
+}
+
 // Per cell and Gauss point: node positions of the isoparametric map (Gauss-Lobatto
 // support points of x + a sin(pi x) sin(pi y) sin(pi z) (1,1,1)), J_q = sum_i x_i (x)
 // grad phi_i(xi_q), and G_q = w_q det J_q J_q^{-1} J_q^{-T}, stored [cell][6][q] in FP64
-// and FP32 (components 00, 11, 22, 01, 02, 12).
+// and FP32 (components 00, 11, 22, 01, 02, 12).  With kfield the position-dependent
+// coefficient at the image x_q = sum_i x_i phi_i(xi_q) of the Gauss point is folded into
+// G_q.  A det J_q that is not positive raises kFlagDetJ in *flag.
 template <int K>
 __global__ void __launch_bounds__(kBlock)
 metric_kernel(double *__restrict__ m64, float *__restrict__ m32, int Nc, double h, double amp,
-              Tab<K + 1, double> tb) {
+              int kfield, double kamp, int *__restrict__ flag, Tab<K + 1, double> tb) {
   constexpr int n = K + 1, n3 = n * n * n;
   __shared__ double S[n * n], Sd[n * n], gll[n], w[n];
   for (int i = threadIdx.x; i < n * n; i += kBlock) {
@@ -44,21 +57,25 @@ metric_kernel(double *__restrict__ m64, float *__restrict__ m32, int Nc, double 
         X[d][i] = (c[d] + gll[i]) * h;
         s1[d][i] = sin(M_PI * X[d][i]);
       }
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, xq[3] = {0, 0, 0};
     for (int i2 = 0; i2 < n; ++i2)
       for (int i1 = 0; i1 < n; ++i1)
         for (int i0 = 0; i0 < n; ++i0) {
           const double disp = amp * s1[0][i0] * s1[1][i1] * s1[2][i2];
           const double xn[3] = {X[0][i0] + disp, X[1][i1] + disp, X[2][i2] + disp};
+          const double phi = S[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2];
           const double dphi[3] = {Sd[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2],
                                   S[q0 * n + i0] * Sd[q1 * n + i1] * S[q2 * n + i2],
                                   S[q0 * n + i0] * S[q1 * n + i1] * Sd[q2 * n + i2]};
-          for (int a = 0; a < 3; ++a)
+          for (int a = 0; a < 3; ++a) {
+            xq[a] += xn[a] * phi;
             for (int b = 0; b < 3; ++b) J[a][b] += xn[a] * dphi[b];
+          }
         }
     const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                        J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(det > 0.0) || !isfinite(det)) atomicOr(flag, int(kFlagDetJ));
     double Ji[3][3];
     Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
     Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
@@ -69,7 +86,7 @@ metric_kernel(double *__restrict__ m64, float *__restrict__ m32, int Nc, double 
     Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
     Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
     Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-    const double wd = w[q0] * w[q1] * w[q2] * det;
+    const double wd = w[q0] * w[q1] * w[q2] * det * (kfield ? cosine_field(xq, kamp) : 1.0);
     const int cc[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
     for (int e = 0; e < 6; ++e) {
       const int a = cc[e][0], b = cc[e][1];
@@ -311,8 +328,9 @@ inline int grid_for(int64_t items, int cap = 65536) {
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s) {
   const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
 #define CASE(K)                                                                                \
-  metric_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.metric64, L.metric32, L.Nc, L.h,        \
-                                                      c.p.curve_amp, shrink_tab<K + 1, double>(c.tab64)); \
+  metric_kernel<K><<<grid_for(items), kBlock, 0, s>>>(                                          \
+      L.metric64, L.metric32, L.Nc, L.h, c.p.curve_amp, c.p.kappa_field == MFL_KAPPA_COSINE,        \
+      c.p.kappa_field_amp, c.flags, shrink_tab<K + 1, double>(c.tab64));                            \
   break
   MFL_DISPATCH_K(c.k, CASE)
 #undef CASE

@@ -119,6 +119,7 @@ struct Context {
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
   double *partials = nullptr;   // kReduceBlocks doubles
   double *scalars = nullptr;    // device scalars (see enum Scalar)
+  int *flags = nullptr;         // device error flags of the setup checks (see enum Flag)
   double *host_scalars = nullptr;   // pinned host mirror
   // the V-cycle on the work vectors r -> z, captured once as a HIP graph on an internal
   // stream and replayed on the caller's stream (use_graphs); rebuilt when the smoother or
@@ -139,6 +140,10 @@ inline int dirichlet_mask(const mfl_params &p) {
 
 enum Scalar { kRZ = 0, kPQ, kAlpha, kBeta, kRR, kBB, kRZnew, kNumScalars = 16 };
 
+// Bits of flags[0], raised by setup kernels: a kappa value that is not finite and positive,
+// a quadrature point of a curved cell with det J <= 0 (or not finite).
+enum Flag { kFlagKappa = 1, kFlagDetJ = 2, kNumFlags = 64 };
+
 // ---- host-side tables -------------------------------------------------------
 void gauss_legendre(int n, double *x, double *w);
 void gauss_lobatto(int n, double *x, double *w);
@@ -158,7 +163,11 @@ hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void 
 int64_t cg_halo_elements(int k, int Nc, bool curved);
 hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *u, const double *lam,
                                 double *grad, hipStream_t s);
+// per-point metric of curved cells (times the position-dependent kappa field when the
+// parameters ask for it); raises kFlagDetJ in c.flags for a non-positive det J
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s);
+// raises `bit` in *flag for every value of v[0..n) that is not finite and positive
+hipError_t launch_check_positive(const double *v, int64_t n, int *flag, int bit, hipStream_t s);
 hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s);
 hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStream_t s);
 // right-hand side of the three-Gaussian example: forcing and Neumann loads (b = 0 first)

@@ -62,7 +62,16 @@ def test_workspace_scales_with_geometry_and_multigrid():
                                 dict(domain_len=0.0), dict(domain_len=-2.0),
                                 dict(dg_jacobi_basis=2),
                                 dict(domain_lo=float("nan")),
-                                dict(geometry=mfl.CURVED, domain_lo=-1.0, domain_len=2.0)])
+                                dict(geometry=mfl.CURVED, domain_lo=-1.0, domain_len=2.0),
+                                dict(kappa_field=2),
+                                dict(kappa_field=mfl.KAPPA_COSINE),
+                                dict(kappa_field=mfl.KAPPA_COSINE, disc=mfl.SIPG),
+                                dict(kappa_field=mfl.KAPPA_COSINE, geometry=mfl.CURVED, kappa_field_amp=-1.0),
+                                dict(kappa_field=mfl.KAPPA_COSINE, geometry=mfl.CURVED,
+                                     kappa_field_amp=float("inf")),
+                                dict(degree=8, cells_per_dim=4, build_mg=True, min_level_cells=4),
+                                dict(degree=7, cells_per_dim=4, build_mg=True, min_level_cells=4,
+                                     disc=mfl.SIPG)])
 def test_invalid_params_rejected(kw):
     base = dict(degree=2, cells_per_dim=8)
     base.update(kw)
@@ -95,3 +104,39 @@ def test_mixed_conditions_and_domain_accepted():
     assert n == 25 ** 3 and c == 512 and ws > 0
     n2, _, ws2 = mfl.query(mfl.make_params(3, 8, bc=mfl.MIXED, disc=mfl.SIPG))
     assert n2 == 512 * 64 and ws2 > 0
+
+
+def test_coarse_size_limit():
+    """The coarsest level takes at most 20000 unknowns (CG: without the Dirichlet DoFs)."""
+    # Q8 on 2^3 cells: 15^3 interior unknowns; Q6 on 3^3 cells: 17^3; both accepted
+    for k, nc in ((8, 2), (6, 3)):
+        mfl.query(mfl.make_params(k, nc, build_mg=True, min_level_cells=nc))
+    # Q8 on 3^3 cells: 23^3 = 12167 accepted; SIPG Q5 on 4^3 cells: 13824 accepted
+    mfl.query(mfl.make_params(8, 3, build_mg=True, min_level_cells=3, bc=mfl.MIXED))
+    mfl.query(mfl.make_params(5, 4, build_mg=True, min_level_cells=4, disc=mfl.SIPG, bc=mfl.MIXED))
+
+
+def test_kappa_field_accepted_on_curved_cg():
+    n, c, ws = mfl.query(mfl.make_params(4, 8, geometry=mfl.CURVED, curve_amp=0.0,
+                                         kappa_field=mfl.KAPPA_COSINE, build_mg=True))
+    assert n == 33 ** 3 and ws > 0
+
+
+def test_default_kappa_field():
+    p = _mfl.Params()
+    assert mfl.lib().mfl_default_params(ctypes.byref(p)) == 0
+    assert p.kappa_field == mfl.KAPPA_CELLWISE and p.kappa_field_amp == 1e6
+
+
+@pytest.mark.parametrize("bad", ["cpu", "dtype", "size", "strided", "not_tensor"])
+def test_check_vector_rejects_without_gpu(bad):
+    """The binding validates every tensor the library writes through (output vectors of
+    apply, vcycle, solve, adjoint_solve and transfer) before calling it."""
+    import torch
+    t = {"cpu": torch.zeros(10, dtype=torch.float64),
+         "dtype": torch.zeros(10, dtype=torch.float32),
+         "size": torch.zeros(9, dtype=torch.float64),
+         "strided": torch.zeros(20, dtype=torch.float64)[::2],
+         "not_tensor": [0.0] * 10}[bad]
+    with pytest.raises(ValueError):
+        mfl.check_vector(t, 10, torch.float64, "x")

@@ -51,7 +51,9 @@ def test_gradient_matches_oracle_small(prec):
 
 
 def test_gradient_finite_differences_q3_32cubed():
-    """CG Q3 on 32^3 cells, FP64 outer / FP32 multigrid, 20 random cells."""
+    """CG Q3 on 32^3 cells, FP64 outer / FP32 multigrid, 20 random cells: central differences
+    with step 1e-4 kappa_c, forward solves to 1e-14, agreement within 1e-5 of each cell's
+    gradient."""
     Nc, k = 32, 3
     prob, b, kap, kap_t = setup_problem(Nc, k, mfl.F32)
     prob.set_kappa(kap_t)
@@ -63,15 +65,15 @@ def test_gradient_finite_differences_q3_32cubed():
     cells = choose_cells(Nc ** 3, 20, SEED_FD_CELLS)
     errs = []
     for c in cells:
-        eps = 1e-3 * kap[c]
+        eps = 1e-4 * kap[c]
         kp, km = kap.copy(), kap.copy()
         kp[c] += eps
         km[c] -= eps
         fd = (objective(prob, b, kp, u_t, 1e-14) - objective(prob, b, km, u_t, 1e-14)) / (2 * eps)
-        errs.append(abs(fd - g[c]))
-    scale = np.abs(g[cells]).max()
-    print("max FD deviation %.3e of max |grad| %.3e" % (max(errs), scale))
-    assert max(errs) <= 1e-4 * scale
+        errs.append(abs(fd - g[c]) / abs(g[c]))
+        print("cell %d: gradient %.6e, central difference %.6e, relative deviation %.2e" % (
+            c, g[c], fd, errs[-1]), flush=True)
+    assert max(errs) <= 1e-5
 
 
 def test_gradcheck_tiny():

@@ -184,22 +184,6 @@ def test_rhs_sine_matches_oracle(k):
         assert rel_err(prob.rhs_sine(), o_cg.rhs(box)) <= 1e-12
 
 
-@pytest.mark.parametrize("k", [2, 3])
-def test_transfer_matches_oracle_embedding(k):
-    prob = mfl.Problem(k, 8, build_mg=True, min_level_cells=2)
-    lev = prob.num_levels - 1
-    fine, coarse = Box(8, k), Box(4, k)
-    P = o_mg.prolongation(coarse, fine)
-    uc = uniform_vector(coarse.n_dofs, 11)
-    uf = uniform_vector(fine.n_dofs, 12)
-    out = t(uf.copy())
-    prob.transfer(lev, 0, t(uc), out)
-    assert rel_err(out, uf + P @ uc) <= 1e-13
-    rc = torch.empty(coarse.n_dofs, dtype=torch.float64, device=DEV)
-    prob.transfer(lev, 1, t(uf), rc)
-    assert rel_err(rc, P.T @ uf) <= 1e-13
-
-
 @pytest.mark.parametrize("k", [2, 4])
 def test_eigenvalue_estimates_match_oracle(k):
     prob = mfl.Problem(k, 8, build_mg=True)
@@ -260,11 +244,12 @@ def test_pcg_error_paths():
     assert its == 0 and x.abs().max().item() == 0.0
 
 
-def test_kappa_gradient_matches_oracle():
-    k, Nc = 2, 4
-    box = Box(Nc, k)
+@pytest.mark.parametrize("k,geom", [(2, 0.0), (3, 0.1), (4, 0.1)])
+def test_kappa_gradient_matches_oracle(k, geom):
+    Nc = 4
+    box = Box(Nc, k, geom)
     kap = kappa_field(box.n_cells)
-    prob = mfl.Problem(k, Nc, kappa=kap, build_mg=True)
+    prob = mfl.Problem(k, Nc, kappa=kap, build_mg=True, geometry=mfl.CURVED if geom else mfl.CARTESIAN)
     u = uniform_vector(box.n_dofs, 31)
     lam = uniform_vector(box.n_dofs, 32)
     g = prob.kappa_gradient(t(u), t(lam))

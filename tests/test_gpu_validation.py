@@ -1,0 +1,62 @@
+"""Failure paths of the setup (Sec. 2 requires kappa > 0): a cellwise kappa that is zero,
+negative, infinite or NaN is rejected with MFL_EINVAL by mfl_setup and mfl_set_kappa (a device
+check), and a rejected mfl_set_kappa leaves the handle's operator unchanged.  The binding
+rejects output tensors that the library would write out of bounds or in the wrong type."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1611_03029_amd as mfl
+from paper_1611_03029_amd import _mfl
+from seeded_inputs import uniform_vector
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("inf"), float("nan")])
+def test_setup_rejects_invalid_kappa(bad):
+    kap = np.ones(4 ** 3)
+    kap[17] = bad
+    with pytest.raises(mfl.MflError) as e:
+        mfl.Problem(2, 4, kappa=kap)
+    assert e.value.code == _mfl.MFL_EINVAL and "kappa" in str(e.value)
+
+
+@pytest.mark.parametrize("bad", [0.0, -2.0, float("nan")])
+def test_set_kappa_rejects_and_keeps_operator(bad):
+    prob = mfl.Problem(3, 4, build_mg=True, kappa=np.full(64, 2.0))
+    u = torch.tensor(uniform_vector(prob.n_dofs, 700), device="cuda")
+    y0 = prob.apply(u).clone()
+    lam0 = prob.level_info(-1)["lambda_max"]
+    kap = np.full(64, 3.0)
+    kap[5] = bad
+    with pytest.raises(mfl.MflError) as e:
+        prob.set_kappa(kap)
+    assert e.value.code == _mfl.MFL_EINVAL
+    # the brick assembly sums shared DoFs in a varying order: equal to rounding
+    assert (prob.apply(u) - y0).abs().max().item() <= 1e-14 * y0.abs().max().item()
+    assert prob.level_info(-1)["lambda_max"] == lam0
+    prob.set_kappa(np.full(64, 3.0))      # a valid kappa is accepted afterwards
+    fresh = mfl.Problem(3, 4, build_mg=True, kappa=np.full(64, 3.0))
+    y1 = fresh.apply(u)
+    assert (prob.apply(u) - y1).abs().max().item() <= 1e-14 * y1.abs().max().item()
+
+
+def test_binding_rejects_bad_outputs():
+    prob = mfl.Problem(2, 4, build_mg=True)
+    b = prob.rhs_sine()
+    for x in (torch.empty(prob.n_dofs - 1, dtype=torch.float64, device="cuda"),
+              torch.empty(prob.n_dofs, dtype=torch.float32, device="cuda"),
+              torch.empty(prob.n_dofs, dtype=torch.float64),
+              torch.empty(2 * prob.n_dofs, dtype=torch.float64, device="cuda")[::2]):
+        with pytest.raises(ValueError):
+            prob.solve(b, x=x)
+        with pytest.raises(ValueError):
+            prob.vcycle(b, x)
+        with pytest.raises(ValueError):
+            prob.apply(b, x)
+    fine = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        prob.transfer(1, 1, fine, torch.empty(5, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        prob.transfer(1, 0, torch.empty(5, dtype=torch.float64, device="cuda"), fine)
