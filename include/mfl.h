@@ -218,6 +218,26 @@ int mfl_adjoint_solve(mfl_handle h, const double *dJdu, double *lambda, double r
 int mfl_kappa_gradient(mfl_handle h, const double *u, const double *lambda, double *grad,
                        void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dst = A src for the continuous Q_k
+ * operator on a Cartesian mesh (p->disc = MFL_DISC_CG, p->geometry = MFL_GEOM_CARTESIAN,
+ * cellwise kappa), the same operator and kernels as mfl_apply, without a handle or a
+ * workspace.  kappa_cells: device array of n_cells positive doubles (not checked), or NULL
+ * for kappa = 1.  src, dst: device vectors of n_dofs values of dtype (must not overlap).
+ * The work-group brick halo records (and kappa in FP32, or the unit kappa) live in a fixed
+ * device array of MFL_NOALLOC_SCRATCH_BYTES per GPU that the library holds from its first
+ * use on that GPU until the process ends; the call makes no allocation.  That array is
+ * shared by every call on the GPU and keeps the last call's contents: calls that overlap on
+ * one GPU (two streams, two host threads) race and must be serialized by the caller.  The
+ * current device must be the stream's.  The first call on a device looks the array's
+ * address up (hipGetSymbolAddress); make it outside graph capture.  Errors: MFL_EINVAL
+ * (params, dtype, NULL or equal src/dst, a mesh whose halo records and kappa need more
+ * than MFL_NOALLOC_SCRATCH_BYTES, e.g. Q6 on 64^3 cells), MFL_EUNSUPPORTED (SIPG, curved
+ * geometry, the position-dependent kappa field), MFL_EHIP.  Asynchronous. */
+#define MFL_NOALLOC_SCRATCH_BYTES (48ll << 20)
+int mfl_apply_noalloc(const mfl_params *p, const double *kappa_cells, int dtype, const void *src, void *dst,
+                      void *stream);
+
 /* Timing of the operator's cell kernel (the dominant kernel of mfl_apply): enable = 1 starts
  * recording a HIP event pair around every cell-kernel launch that mfl_apply enqueues (on the
  * caller's stream, up to 8192 launches); enable = 0 stops, synchronizes on the recorded events

@@ -4,9 +4,10 @@ The compute path is libmfl.so (hand-written HIP kernels behind the C ABI in
 include/mfl.h); this package only marshals torch tensors into it.
 """
 from ._mfl import (CARTESIAN, CG, CURVED, DIRICHLET, F32, F64, KAPPA_CELLWISE, KAPPA_COSINE, MIXED,
-                   NEUMANN, SIPG, MflError, Problem, check_vector, lib, make_params, query)
+                   NEUMANN, SIPG, MflError, Problem, apply_noalloc, check_vector, lib, make_params,
+                   query)
 from .autograd import PoissonSolve
 
 __all__ = ["Problem", "PoissonSolve", "MflError", "lib", "make_params", "query", "CG", "SIPG",
            "CARTESIAN", "CURVED", "DIRICHLET", "NEUMANN", "MIXED", "F64", "F32", "KAPPA_CELLWISE",
-           "KAPPA_COSINE", "check_vector"]
+           "KAPPA_COSINE", "check_vector", "apply_noalloc"]

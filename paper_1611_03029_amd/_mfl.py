@@ -75,6 +75,7 @@ SIGNATURES = {
     "mfl_adjoint_solve": (ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_int, IP, DP, P]),
     "mfl_kappa_gradient": (ctypes.c_int, [P, P, P, P, P]),
     "mfl_profile": (ctypes.c_int, [P, ctypes.c_int, IP, DP]),
+    "mfl_apply_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), P, ctypes.c_int, P, P, P]),
     "mfl_destroy": (ctypes.c_int, [P]),
     "mfl_last_error": (ctypes.c_char_p, []),
 }
@@ -143,6 +144,25 @@ def check_vector(t, n, dtype, name):
     if t.numel() != n:
         raise ValueError("%s must hold %d values (got %d)" % (name, n, t.numel()))
     return t
+
+
+NOALLOC_SCRATCH_BYTES = 48 << 20
+
+
+def apply_noalloc(params, src, dst, kappa=None):
+    """dst = A src through mfl_apply_noalloc (continuous Q_k, Cartesian cells): no handle,
+    no workspace; the library's fixed per-GPU scratch array holds its halo records.  kappa:
+    None or a float64 CUDA tensor of n_cells values."""
+    n, cells, _ = query(params)
+    dtype = F32 if torch.is_tensor(src) and src.dtype == torch.float32 else F64
+    check_vector(src, n, _DT[dtype], "src")
+    check_vector(dst, n, _DT[dtype], "dst")
+    kptr = None
+    if kappa is not None:
+        check_vector(kappa, cells, torch.float64, "kappa")
+        kptr = _ptr(kappa)
+    _check(lib().mfl_apply_noalloc(ctypes.byref(params), kptr, dtype, _ptr(src), _ptr(dst), _stream()))
+    return dst
 
 
 def query(params):

@@ -2,10 +2,12 @@
 // V-cycle and the preconditioned conjugate gradient solver (Sec. 4.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -675,6 +677,37 @@ int setup_flags(Context &c, hipStream_t s) {
 
 struct mfl_context : public Context {};
 
+// ---- the allocation-free apply ---------------------------------------------------------
+// Device memory of mfl_apply_noalloc: one fixed array per GPU, held from the library's
+// first use on that GPU until the process ends.  Host code never names it except in
+// hipGetSymbolAddress: its device address differs per GPU and is looked up once per device.
+static __device__ __align__(256) char scratch[MFL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+int scratch_address(char **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MFL_EUNSUPPORTED, "device index %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MFL_EHIP, "hipGetSymbolAddress of the scratch array: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return MFL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mfl_default_params(mfl_params *p) {
@@ -812,6 +845,55 @@ int mfl_apply(mfl_handle h, int level, int dtype, const void *src, void *dst, vo
       (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
     return fail(MFL_EINVAL, "SIPG vectors with an even number of points per direction must be 16-byte aligned");
   return apply_level(*h, l, dtype, src, dst, as_stream(stream), true);
+}
+
+int mfl_apply_noalloc(const mfl_params *p, const double *kappa_cells, int dtype, const void *src, void *dst,
+                      void *stream) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (p->disc != MFL_DISC_CG || p->geometry != MFL_GEOM_CARTESIAN || p->kappa_field != MFL_KAPPA_CELLWISE)
+    return fail(MFL_EUNSUPPORTED, "mfl_apply_noalloc covers the continuous operator on Cartesian cells "
+                                  "with a cellwise kappa");
+  if (dtype != MFL_F64 && dtype != MFL_F32) return fail(MFL_EINVAL, "unknown dtype %d", dtype);
+  if (!src || !dst) return fail(MFL_EINVAL, "src/dst is NULL");
+  if (src == dst) return fail(MFL_EINVAL, "src and dst must not overlap");
+  Context c;
+  c.p = *p;
+  c.p.build_mg = 0;
+  c.k = p->degree;
+  c.n = p->degree + 1;
+  Level L;
+  L.Nc = p->cells_per_dim;
+  L.N1 = c.k * L.Nc + 1;
+  L.ncells = int64_t(L.Nc) * L.Nc * L.Nc;
+  L.ndofs = int64_t(L.N1) * L.N1 * L.N1;
+  L.h = p->domain_len / L.Nc;
+  // scratch layout: halo records, then kappa in the apply's precision (absent for FP64 with
+  // a caller kappa), each 256-byte aligned
+  const int64_t es = dtype == MFL_F64 ? 8 : 4;
+  const int64_t halo_bytes = (cg_halo_elements(c.k, L.Nc, false) * es + 255) / 256 * 256;
+  const bool own_kappa = !(dtype == MFL_F64 && kappa_cells);
+  const int64_t need = halo_bytes + (own_kappa ? L.ncells * es : 0);
+  if (need > MFL_NOALLOC_SCRATCH_BYTES)
+    return fail(MFL_EINVAL, "this mesh needs %lld bytes of scratch; mfl_apply_noalloc has %lld",
+                (long long)need, (long long)MFL_NOALLOC_SCRATCH_BYTES);
+  char *ptr = nullptr;
+  if ((rc = scratch_address(&ptr))) return rc;
+  hipStream_t s = as_stream(stream);
+  L.halo = ptr;
+  if (dtype == MFL_F64) {
+    L.kappa64 = own_kappa ? reinterpret_cast<double *>(ptr + halo_bytes) : const_cast<double *>(kappa_cells);
+    if (own_kappa) HIP_TRY(launch_fill(L.kappa64, MFL_F64, L.ncells, 1.0, s));
+  } else {
+    L.kappa32 = reinterpret_cast<float *>(ptr + halo_bytes);
+    if (kappa_cells)
+      HIP_TRY(launch_cast(kappa_cells, MFL_F64, L.kappa32, MFL_F32, L.ncells, s));
+    else
+      HIP_TRY(launch_fill(L.kappa32, MFL_F32, L.ncells, 1.0, s));
+  }
+  HIP_TRY(launch_cg_apply(c, L, dtype, src, dst, s));
+  HIP_TRY(launch_cg_halo_add(c, L, dtype, dst, s));
+  return MFL_OK;
 }
 
 int mfl_profile(mfl_handle h, int enable, int *launches, double *total_ms) {
