@@ -23,10 +23,17 @@ Also reported, outside the timed region:
                 tolerance 1e-10 relative residual, sine right-hand side, degrees 2..6;
   adjoint       forward solve + adjoint solve + gradient kernel, CG Q3 on 32^3 cells,
                 FP32 V-cycle;
-  cpu_baseline  the CPU oracle (element-by-element dense element matrices) on a bounded
-                sample of rows of the timed workload.
+  kappa_field_apply  the same apply with the variable coefficient of Sec. 4.3 folded into the
+                metric (same kernel);
+  cpu_baseline  the CPU oracle on the host: its assembled CSR matrix of the timed operator
+                (16^3 curved cells) applied over all host threads, and its GMG-PCG solve of
+                CG Q2 on 32^3 cells.
+
+  roofline.frac is the operator cell kernel's (HIP events around its launches); step_frac is
+  the whole application (cell kernel plus halo addition) at the timed step's rate.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve-degrees 2,3,4,5,6]
+       python bench.py --reduce NAME DIR [DIR]   (rocprofv3 CSV output -> summary under profiles/)
        python bench.py --sipg-only [--steps K]     (the SIPG applies alone, for profiling)
        python bench.py --solve-only [--solve-degrees 4]   (the GMG-PCG solves alone, for profiling)
 """
@@ -273,30 +280,363 @@ def adjoint_config():
             "note": "includes two set_kappa rebuilds (diagonals, eigenvalue estimates)"}
 
 
-def cpu_baseline(budget_s=15.0):
-    """The oracle's element-by-element apply (dense element matrices from per-point
-    integrals) on sampled rows of the 64^3 curved Q4 workload, one host thread."""
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cells=16, reps=5, products=20):
+    """The CPU oracle on the host cores of this machine.
+
+    apply: the oracle's assembled CSR matrix of the timed operator (CG Q4, curved cells,
+    assembled from dense element matrices) applied with torch's CSR product over all host
+    threads; `cells`^3 cells instead of 64^3 (the 64^3 matrix would hold about 3.7e9 nonzeros,
+    44 GB), which leaves the CSR product out of cache, so its DoFs/s carries over.  Min and
+    median over `reps` runs of `products` products; assembly is not timed.
+    solve: the oracle's textbook GMG-PCG (scipy CSR, one thread) on CG Q2 with 32^3 cells,
+    sine right-hand side, tolerance 1e-10: setup (assembly of every level, eigenvalue
+    estimates) and solve wall times."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    import torch
 
     from oracle import cg as o_cg
+    from oracle import mg as o_mg
     from oracle.mesh import Box
     from seeded_inputs import SEED_CG_Q4_CURVED, uniform_vector
 
-    box = Box(64, 4, 0.1)
-    u = uniform_vector(box.n_dofs, SEED_CG_Q4_CURVED)
-    rng = np.random.default_rng(99)
-    done, t_used = 0, 0.0
-    with threadpool_limits(1):
-        while t_used < budget_s:
-            rows = rng.choice(box.n_dofs, 64, replace=False)
-            t0 = time.perf_counter()
-            o_cg.apply_rows(box, u, rows)
-            t_used += time.perf_counter() - t0
-            done += len(rows)
-    return {"value": done / t_used, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
-            "sample": "%d sampled rows of CG Q4 64^3 curved (dense element matrices per "
-                      "cell, element-by-element), %.1f s on 1 host thread" % (done, t_used)}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    torch.set_num_threads(threads)
+    t0 = time.perf_counter()
+    box = Box(cells, 4, 0.1)
+    A = o_cg.assemble(box)
+    assemble_s = time.perf_counter() - t0
+    nnz = int(A.nnz)
+    At = torch.sparse_csr_tensor(torch.from_numpy(A.indptr.astype(np.int64)),
+                                 torch.from_numpy(A.indices.astype(np.int64)),
+                                 torch.from_numpy(A.data), size=A.shape)
+    u = torch.from_numpy(uniform_vector(box.n_dofs, SEED_CG_Q4_CURVED))
+    y = At @ u
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for _ in range(products):
+            y = At @ u
+        times.append((time.perf_counter() - t0) / products)
+    times.sort()
+    del At, A, y
+    t0 = time.perf_counter()
+    mg = o_mg.Multigrid(32, 2)
+    setup_s = time.perf_counter() - t0
+    fine = mg.levels[-1]
+    b = o_cg.rhs(fine["box"])
+    t0 = time.perf_counter()
+    _, its, res, _ = o_mg.pcg(fine["A"], b, mg.vcycle, tol=1e-10)
+    solve_s = time.perf_counter() - t0
+    return {"value": box.n_dofs / times[0], "unit": "DoFs/s", "cores": threads, "kind": "oracle",
+            "sample": "CSR product of the oracle's assembled CG Q4 operator on %d^3 curved cells "
+                      "(%d DoFs, %d nonzeros; torch CSR over %d host threads), min of %d runs of %d "
+                      "products" % (cells, box.n_dofs, nnz, threads, reps, products),
+            "median_dofs_per_s": box.n_dofs / times[len(times) // 2],
+            "ms_per_product_min": times[0] * 1e3,
+            "assembly_s": assemble_s,
+            "nproc": os.cpu_count(), "cpu_model": host_cpu_model(),
+            "gmg_pcg_q2_32cubed": {"n_dofs": fine["box"].n_dofs, "setup_s": setup_s, "solve_s": solve_s,
+                                   "iterations": its, "final_rel_residual": res,
+                                   "threads": "1 (scipy CSR products)"}}
+
+
+# ---- reduction of rocprofv3 output (CSV) into the summaries kept under profiles/ ----------
+
+def _find_csv(path, suffix):
+    """`path` itself, or the one file under the directory `path` whose name ends in `suffix`."""
+    import glob
+    if os.path.isfile(path):
+        return path
+    hits = sorted(glob.glob(os.path.join(path, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit("no *%s under %s" % (suffix, path))
+    return hits[-1]
+
+
+def _col(row, name):
+    for k in row:
+        if k.lower() == name:
+            return row[k]
+    raise KeyError(name)
+
+
+def counter_dispatches(path, counter=None, resources=None):
+    """Per-dispatch counter values of a rocprofv3 --pmc CSV (counter_collection.csv):
+    {(dispatch id, counter): [kernel name, grid size, value summed over the rows]}.
+    resources (a dict) receives {kernel name: (VGPRs, AGPRs, SGPRs, LDS bytes, work-group size)}."""
+    import csv
+    out = {}
+    with open(_find_csv(path, "counter_collection.csv"), newline="") as f:
+        for r in csv.DictReader(f):
+            name = _col(r, "counter_name")
+            if counter is not None and name != counter:
+                continue
+            key = (int(_col(r, "dispatch_id")), name)
+            rec = out.setdefault(key, [_col(r, "kernel_name"), int(float(_col(r, "grid_size"))), 0.0])
+            rec[2] += float(_col(r, "counter_value"))
+            if resources is not None:
+                resources[rec[0]] = tuple(int(float(_col(r, c))) for c in (
+                    "vgpr_count", "accum_vgpr_count", "sgpr_count", "lds_block_size", "workgroup_size"))
+    return out
+
+
+def waves_per_simd(vgprs, agprs, lds, wg):
+    """Resident waves per SIMD from the register and LDS use (512 registers per lane of a
+    SIMD shared by VGPRs and AGPRs in granules of 8; 160 KiB of LDS per CU; 4 SIMDs per CU;
+    at most 8 waves per SIMD)."""
+    regs = max(8, -(-(vgprs + agprs) // 8) * 8)
+    by_regs = 512 // regs
+    waves_wg = -(-wg // 64)
+    by_lds = (160 * 1024 // lds) * waves_wg / 4.0 if lds else 8
+    return min(8, by_regs, by_lds)
+
+
+def short_kernel_name(name):
+    """Kernel name without namespaces and argument list: apply_brick_kernel<4, double, true, 0>."""
+    n = name
+    for pre in ("(anonymous namespace)::", "void ", "mfl::"):
+        n = n.replace(pre, "")
+    return n.split("(")[0].strip()
+
+
+def reduce_traffic(fetch, write, calib_bytes, kernels, algorithmic, workload, commands, out_path):
+    """HBM bytes per dispatch of each kernel whose name contains one of `kernels` (dict
+    substring -> {"algorithmic_bytes": ...}, optionally "grid": the launch's grid size), from a
+    FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch).  Each counter is scaled by what it
+    reads for the largest plain device copy in the same run (__amd_rocclr_copyBuffer of
+    `calib_bytes` bytes each way)."""
+    import statistics
+    f = counter_dispatches(fetch, "FETCH_SIZE")
+    w = counter_dispatches(write, "WRITE_SIZE")
+
+    def calib(recs):
+        vals = [v for (name, _g, v) in recs.values() if "copyBuffer" in name]
+        if not vals:
+            raise SystemExit("no copyBuffer dispatch for the calibration")
+        return max(vals)
+
+    fk, wk = calib(f), calib(w)
+    fs, ws = calib_bytes / (fk * 1024.0), calib_bytes / (wk * 1024.0)
+    res = {"workload": workload, "kernel_source_hash": kernel_source_hash(), "commands": commands,
+           "calibration": {"kernel": "__amd_rocclr_copyBuffer (largest device copy of the run)",
+                           "bytes_each_way": calib_bytes, "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk,
+                           "fetch_scale": fs, "write_scale": ws},
+           "kernels": {}}
+    for label, spec in kernels.items():
+        def pick(recs):
+            return [v for (name, g, v) in recs.values()
+                    if spec["match"] in short_kernel_name(name) and ("grid" not in spec or g == spec["grid"])]
+        fv, wv = pick(f), pick(w)
+        if not fv or not wv:
+            raise SystemExit("kernel %s not found" % spec["match"])
+        rd = statistics.median(fv) * 1024.0 * fs
+        wr = statistics.median(wv) * 1024.0 * ws
+        rec = {"match": spec["match"], "dispatches": [len(fv), len(wv)],
+               "FETCH_SIZE_KiB_per_dispatch": statistics.median(fv),
+               "WRITE_SIZE_KiB_per_dispatch": statistics.median(wv),
+               "hbm_read_bytes": rd, "hbm_write_bytes": wr, "hbm_bytes_per_launch": rd + wr}
+        if "algorithmic_bytes" in spec:
+            rec["algorithmic_bytes"] = spec["algorithmic_bytes"]
+            rec["hbm_over_algorithmic"] = (rd + wr) / spec["algorithmic_bytes"]
+        res["kernels"][label] = rec
+    if algorithmic is not None:
+        res["algorithmic_bytes_per_launch"] = algorithmic
+        first = next(iter(res["kernels"].values()))
+        res["hbm_bytes_per_launch"] = first["hbm_bytes_per_launch"]
+    with open(out_path, "w") as fo:
+        json.dump(res, fo, indent=1)
+    print("wrote", out_path)
+
+
+def summarize_sq(path, groups, title, command, out_path):
+    """Median over dispatches of SQ (and TA/TD/TCP/TCC) counters per kernel group
+    (substring, label[, grid size]), with the ratios used in the design notes and the
+    register/LDS use and resident waves per SIMD, as a text summary."""
+    import statistics
+    res = {}
+    recs = counter_dispatches(path, resources=res)
+    lines = ["# rocprofv3 SQ counters: " + title, "# command: " + command,
+             "# kernel source hash (bench.kernel_source_hash): " + kernel_source_hash(),
+             "# median over dispatches of the per-dispatch sums; ratios are between counters of the same unit", ""]
+    for grp in groups:
+        match, label = grp[0], grp[1]
+        grid = grp[2] if len(grp) > 2 else None
+        vals, kn = {}, None
+        for (_d, cname), (kname, g, v) in recs.items():
+            if match in short_kernel_name(kname) and (grid is None or g == grid):
+                vals.setdefault(cname, []).append(v)
+                kn = kname
+        if not vals:
+            continue
+        med = {c: statistics.median(v) for c, v in vals.items()}
+        lines.append("## %s (%d dispatches%s)" % (label, max(len(v) for v in vals.values()),
+                                                   "" if grid is None else ", grid %d" % grid))
+        if kn in res:
+            vg, ag, sg, lds, wg = res[kn]
+            lines.append("resources: %d VGPRs, %d AGPRs, %d SGPRs, %d B LDS per work-group of %d; "
+                         "%.2g waves per SIMD resident" % (vg, ag, sg, lds, wg, waves_per_simd(vg, ag, lds, wg)))
+        for c in sorted(med):
+            lines.append("%-30s %14.6g" % (c, med[c]))
+        cyc = med.get("SQ_WAVE_CYCLES")
+        for c in ("SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_ANY",
+                  "SQ_WAIT_INST_LDS", "SQ_INST_CYCLES_VMEM_RD", "SQ_INST_CYCLES_VMEM_WR"):
+            if cyc and c in med:
+                lines.append("%-40s %8.3f" % (c + " / SQ_WAVE_CYCLES", med[c] / cyc))
+        if "TCC_HIT_sum" in med and med.get("TCC_HIT_sum", 0) + med.get("TCC_MISS_sum", 0) > 0:
+            lines.append("%-40s %8.3f" % ("L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS)",
+                                          med["TCC_HIT_sum"] / (med["TCC_HIT_sum"] + med["TCC_MISS_sum"])))
+        if "SQ_LDS_BANK_CONFLICT" in med and med.get("SQ_INSTS_LDS"):
+            lines.append("%-40s %8.3f" % ("SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS",
+                                          med["SQ_LDS_BANK_CONFLICT"] / med["SQ_INSTS_LDS"]))
+        lines.append("")
+    open(out_path, "w").write("\n".join(lines))
+    print("wrote", out_path)
+
+
+def summarize_stats(path, title, command, out_path, top=25):
+    """Kernel statistics of a rocprofv3 --kernel-trace --stats run as a text table."""
+    import csv
+    rows = []
+    with open(_find_csv(path, "kernel_stats.csv"), newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append((short_kernel_name(_col(r, "name")), int(_col(r, "calls")),
+                         float(_col(r, "averagens")), float(_col(r, "totaldurationns")),
+                         float(_col(r, "percentage"))))
+    rows.sort(key=lambda x: -x[3])
+    lines = ["# rocprofv3 kernel statistics: " + title, "# command: " + command,
+             "# kernel source hash (bench.kernel_source_hash): " + kernel_source_hash(),
+             "%-58s %8s %12s %14s %8s" % ("kernel", "calls", "average_ns", "total_ns", "percent")]
+    for n, c, a, t, pc in rows[:top]:
+        lines.append("%-58s %8d %12.0f %14.0f %8.2f" % (n[:58], c, a, t, pc))
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("wrote", out_path)
+
+
+# How each committed summary under profiles/ is made: the rocprofv3 runs (R = repository
+# root on the GPU machine, outputs under gpurun_out/) and the reduction that turns their CSV
+# output into the summary (`python bench.py --reduce NAME DIR [DIR]`).
+_BENCH_Q4 = "python3 $R/bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline"
+_SQ = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+       "SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT")
+_SOLVE_Q4 = "python3 $R/bench.py --solve-only --solve-degrees 4"
+_SIPG = "python3 $R/bench.py --sipg-only --steps 5"
+_SQ2 = "SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_INST_CYCLES_VMEM_RD SQ_INSTS_VMEM_RD TA_BUSY_avr TD_TD_BUSY_sum"
+_TCC = "TCC_HIT_sum TCC_MISS_sum"
+REDUCTIONS = {
+    "cg_apply_traffic": {
+        "out": "profiles/cg_apply_q4_64cubed_curved_traffic.json",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                 "-d $R/gpurun_out/pmc_fetch -o run -- " + _BENCH_Q4,
+                 "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                 "-d $R/gpurun_out/pmc_write -o run -- " + _BENCH_Q4]},
+    "cg_apply_sq": {
+        "out": "profiles/cg_apply_q4_64cubed_curved_sq_counters.txt",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ + " --output-format csv "
+                 "-d $R/gpurun_out/pmc_sq -o run -- " + _BENCH_Q4]},
+    "cg_solve_sq": {
+        "out": "profiles/gmg_pcg_q4_64cubed_sq_counters.txt",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ + " --output-format csv "
+                 "-d $R/gpurun_out/solve_sq -o run -- " + _SOLVE_Q4,
+                 "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ2 + " --output-format csv "
+                 "-d $R/gpurun_out/solve_sq2 -o run -- " + _SOLVE_Q4]},
+    "cg_solve_traffic": {
+        "out": "profiles/gmg_pcg_q4_64cubed_traffic.json",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                 "-d $R/gpurun_out/solve_fetch -o run -- " + _SOLVE_Q4,
+                 "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                 "-d $R/gpurun_out/solve_write -o run -- " + _SOLVE_Q4]},
+    "cg_solve_stats": {
+        "out": "profiles/gmg_pcg_q4_64cubed_kernel_stats.txt",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+                 "-d $R/gpurun_out/solve_ktrace -o run -- " + _SOLVE_Q4]},
+    "sipg_sq": {
+        "out": "profiles/sipg_apply_q3_q5_sq_counters.txt",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ + " --output-format csv "
+                 "-d $R/gpurun_out/sipg_sq -o run -- " + _SIPG,
+                 "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ2 + " --output-format csv "
+                 "-d $R/gpurun_out/sipg_sq2 -o run -- " + _SIPG,
+                 "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _TCC + " --output-format csv "
+                 "-d $R/gpurun_out/sipg_tcc -o run -- " + _SIPG]},
+    "cg_apply_stats": {
+        "out": "profiles/cg_apply_q4_64cubed_curved_kernel_stats.txt",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+                 "-d $R/gpurun_out/prof_ktrace -o run -- python3 $R/bench.py --steps 20 --warmup 2 "
+                 "--no-extras --no-cpu-baseline"]},
+}
+
+
+def run_reduction(name, dirs):
+    spec = REDUCTIONS[name]
+    cmd = " ; ".join(spec["runs"]) + "  (R = repository root)"
+    out = os.path.join(ROOT, spec["out"])
+    if name == "cg_apply_traffic":
+        n, cells, q = 257 ** 3, 64 ** 3, 125
+        alg = apply_bytes(n, cells, q, 8)
+        reduce_traffic(dirs[0], dirs[1], 8 * n,
+                       {"apply_brick_kernel<4,double,curved>": {"match": "apply_brick_kernel<4, double, true",
+                                                                "algorithmic_bytes": alg},
+                        "halo_add_kernel<4,double>": {"match": "halo_add_kernel<4, double>"}},
+                       alg, "CG Q4 operator apply, 64^3 curved cells (257^3 DoFs), FP64",
+                       spec["runs"], out)
+    elif name == "cg_apply_sq":
+        summarize_sq(dirs[0], [("apply_brick_kernel<4, double, true", "FP64"),
+                               ("apply_brick_kernel<4, float, true", "FP32"),
+                               ("halo_add_kernel<4, double>", "halo addition, FP64")],
+                     "CG Q4 operator kernel, 64^3 curved cells (257^3 DoFs)", cmd, out)
+    elif name == "cg_solve_sq":
+        fine = 8192 * 256   # work-items of the 64^3 level's operator launch (8192 bricks)
+        groups = [("apply_brick_kernel<4, double, false", "Cartesian operator, FP64, 64^3 level", fine),
+                  ("apply_brick_kernel<4, float, false", "Cartesian operator, FP32, 64^3 level", fine),
+                  ("cheb_halo_kernel<4, double>", "Chebyshev update + halo, FP64, 64^3 level", 2097152),
+                  ("cheb_halo_kernel<4, float>", "Chebyshev update + halo, FP32, 64^3 level", 2097152),
+                  ("restrict_xy_kernel<4, double>", "restriction x-y pass, FP64"),
+                  ("restrict_xy_kernel<4, float>", "restriction x-y pass, FP32"),
+                  ("restrict_z_kernel<4, double", "restriction z pass, FP64"),
+                  ("prolong_xy_kernel<4, double>", "prolongation x-y pass, FP64"),
+                  ("prolong_xy_kernel<4, float>", "prolongation x-y pass, FP32"),
+                  ("prolong_z_kernel<4, double", "prolongation z pass, FP64")]
+        for d in dirs[1:]:
+            pass
+        summarize_sq(dirs[0], groups, "GMG-PCG solve kernels, CG Q4 on 64^3 Cartesian cells "
+                     "(FP64 and FP32 V-cycles)", cmd, out)
+        if len(dirs) > 1:
+            summarize_sq(dirs[1], groups, "GMG-PCG solve kernels, CG Q4 on 64^3 Cartesian cells, waits, "
+                         "vector-memory cycles, texture units", cmd, out.replace(".txt", "_2.txt"))
+    elif name == "cg_solve_traffic":
+        n = 257 ** 3
+        kern = {"apply_brick_kernel<4,double,cartesian>": {"match": "apply_brick_kernel<4, double, false",
+                                                           "grid": 8192 * 256, "algorithmic_bytes": 16 * n},
+                "apply_brick_kernel<4,float,cartesian>": {"match": "apply_brick_kernel<4, float, false",
+                                                          "grid": 8192 * 256, "algorithmic_bytes": 8 * n},
+                "cheb_halo_kernel<4,float>": {"match": "cheb_halo_kernel<4, float>", "grid": 2097152,
+                                              "algorithmic_bytes": 28 * n},
+                "cheb_halo_kernel<4,double>": {"match": "cheb_halo_kernel<4, double>", "grid": 2097152,
+                                               "algorithmic_bytes": 56 * n}}
+        reduce_traffic(dirs[0], dirs[1], 8 * n, kern, None,
+                       "GMG-PCG solve, CG Q4 on 64^3 Cartesian cells, FP64 and FP32 V-cycles",
+                       spec["runs"], out)
+    elif name == "cg_solve_stats":
+        summarize_stats(dirs[0], "GMG-PCG solves of the sine problem, CG Q4 on 64^3 Cartesian cells, "
+                        "FP64 and FP32 V-cycles, two solves each", cmd, out, top=40)
+    elif name == "sipg_sq":
+        groups = [("sipg_kernel<3, double>", "SIPG Q3, FP64"), ("sipg_kernel<5, double>", "SIPG Q5, FP64")]
+        summarize_sq(dirs[0], groups, "SIPG operator kernel, Q3 and Q5 on 32^3 and 64^3 cells", cmd, out)
+        for i, d in enumerate(dirs[1:]):
+            summarize_sq(d, groups, "SIPG operator kernel, Q3 and Q5 on 32^3 and 64^3 cells", cmd,
+                         out.replace(".txt", "_%d.txt" % (i + 2)))
+    elif name == "cg_apply_stats":
+        summarize_stats(dirs[0], "CG Q4 operator, 64^3 curved cells (257^3 DoFs), FP64 and FP32 applies "
+                        "(warm-up, timed and repetition-protocol applies; setup kernels once)", cmd, out)
 
 
 def main():
@@ -305,7 +645,11 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--solve-degrees", default="2,3,4,5,6")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-cells", type=int, default=16,
+                    help="cells per direction of the oracle's CSR matrix timed on the host")
+    ap.add_argument("--reduce", nargs="+", metavar=("NAME", "DIR"),
+                    help="turn rocprofv3 CSV output into the summary NAME under profiles/ "
+                         "(names: %s); no GPU needed" % ", ".join(sorted(REDUCTIONS)))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed step and FP32 apply")
     ap.add_argument("--sipg-only", action="store_true",
@@ -313,6 +657,9 @@ def main():
     ap.add_argument("--solve-only", action="store_true",
                     help="only the GMG-PCG solves of --solve-degrees (a profiling target; prints their JSON)")
     args = ap.parse_args()
+    if args.reduce:
+        run_reduction(args.reduce[0], args.reduce[1:])
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path is single-GPU (multi-GPU sharding is a "
               "design note, not implemented); run with --gpus 1", file=sys.stderr)
@@ -347,7 +694,19 @@ def main():
     y32 = torch.empty_like(u32)
     ms32, kern32, _ = time_applies(prob, u32, y32, max(args.steps // 2, 10), args.warmup)
     bytes32 = apply_bytes(n, cells, q, 4)
-    del prob, u32, y32, y64
+    del prob, u32, y32
+    torch.cuda.empty_cache()
+    # the variable-coefficient curved case: the coefficient of Sec. 4.3 folded into the metric,
+    # so the same kernel and bytes as the timed step
+    probk = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1, kappa_field=mfl.KAPPA_COSINE,
+                        kappa_field_amp=1e6)
+    msk, kernk, _ = time_applies(probk, u64, y64, max(args.steps // 2, 10), args.warmup)
+    kfield = {"ms_per_step": msk, "dofs_per_s": n / (msk * 1e-3), "kernel_ms": kernk,
+              "achieved_GBs": bytes64 / (kernk * 1e-3) / 1e9,
+              "frac": bytes64 / (kernk * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "coefficient": "1 + 1e6 prod_e cos^2(2 pi x_e + 0.1 e) at every Gauss point, folded into the metric"}
+    del probk, y64
+    progress("variable-coefficient applies done")
     calib = calibration_copy(n)
     del u64
     torch.cuda.empty_cache()
@@ -373,12 +732,15 @@ def main():
                      "measured_GBs": None if traffic is None else traffic / (kern_ms * 1e-3) / 1e9,
                      "kernel": "apply_brick_kernel<4,double,curved>", "kernel_ms": kern_ms,
                      "algorithmic_bytes": bytes64, "timed_launches": launches,
-                     "kernel_source_hash": kernel_source_hash()},
+                     "kernel_source_hash": kernel_source_hash(),
+                     "step_frac": bytes64 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "step_frac_protocol_min": bytes64 / (protocol["min_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "equiv_dofs_per_s": cells * k ** 3 / (ms_step * 1e-3),
         "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32,
                        "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
                        "frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "timing_protocol": protocol,
+        "kappa_field_apply": kfield,
         "calibration_copy": calib,
         "paper_context": {"cg_curved_q4_dofs_per_s": 4.58e8,
                           "hardware": "2x14-core Xeon E5-2690 v4 (Broadwell), FP64, 393216-cell shell"},
@@ -399,7 +761,7 @@ def main():
         result["paper_example"] = paper_example()
         progress("paper example solves done")
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_cells)
         progress("CPU oracle baseline done")
     print(json.dumps(result))
 
