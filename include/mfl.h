@@ -239,10 +239,11 @@ int mfl_apply_noalloc(const mfl_params *p, const double *kappa_cells, int dtype,
                       void *stream);
 
 /* Timing of the operator's cell kernel (the dominant kernel of mfl_apply): enable = 1 starts
- * recording a HIP event pair around every cell-kernel launch that mfl_apply enqueues (on the
- * caller's stream, up to 8192 launches); enable = 0 stops, synchronizes on the recorded events
- * and returns the number of timed launches and their summed duration in milliseconds.
- * Outputs may be NULL. */
+ * timing every cell-kernel launch that mfl_apply enqueues (up to 8192 launches) with a HIP
+ * event pair that the launch's own dispatch records (hipExtLaunchKernelGGL: no packets are
+ * added between kernels); enable = 0 stops, synchronizes on the recorded events and returns
+ * the number of timed launches and their summed duration in milliseconds.  Outputs may be
+ * NULL. */
 int mfl_profile(mfl_handle h, int enable, int *launches, double *total_ms);
 
 /* Release the handle (the workspace stays owned by the caller). */

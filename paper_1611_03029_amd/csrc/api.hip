@@ -166,6 +166,10 @@ int64_t layout(Context &c, char *base) {
       L.ax = b.take<char>(L.ndofs * es);
       L.d = b.take<char>(L.ndofs * es);
       if (p.disc == MFL_DISC_SIPG && p.dg_jacobi_basis == MFL_DG_JACOBI_GLL) L.x2 = b.take<char>(L.ndofs * es);
+      if (cg && l > 0) {
+        const int64_t N1c = c.levels[l - 1].N1;
+        L.tbuf = b.take<double>(int64_t(L.N1) * N1c * N1c);
+      }
     }
   }
   {
@@ -252,13 +256,16 @@ int apply_level(Context &c, int l, int dtype, const void *src, void *dst, hipStr
     c.prof_start.push_back(a);
     c.prof_stop.push_back(b);
   }
-  if (rec) HIP_TRY(hipEventRecord(c.prof_start[c.prof_used], s));
-  if (c.p.disc == MFL_DISC_SIPG) {
-    HIP_TRY(launch_sipg_apply(c, L, dtype, src, dst, s));
-  } else {
-    HIP_TRY(launch_cg_apply(c, L, dtype, src, dst, s));
+  LaunchEvents ev;
+  if (rec) {
+    ev.start = c.prof_start[c.prof_used];
+    ev.stop = c.prof_stop[c.prof_used++];
   }
-  if (rec) HIP_TRY(hipEventRecord(c.prof_stop[c.prof_used++], s));
+  if (c.p.disc == MFL_DISC_SIPG) {
+    HIP_TRY(launch_sipg_apply(c, L, dtype, src, dst, s, rec ? &ev : nullptr));
+  } else {
+    HIP_TRY(launch_cg_apply(c, L, dtype, src, dst, s, -1, rec ? &ev : nullptr));
+  }
   if (c.p.disc == MFL_DISC_CG && halo) HIP_TRY(launch_cg_halo_add(c, L, dtype, dst, s));
   return MFL_OK;
 }

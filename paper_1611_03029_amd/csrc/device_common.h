@@ -1,6 +1,7 @@
 // Device helpers shared by the kernels of the library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -15,6 +16,16 @@ namespace mfl {
 __device__ __forceinline__ int xcd_block(int bid, int nblk) {
   const int q = nblk / 8, r = nblk % 8, x = bid % 8, j = bid / 8;
   return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
+// kernel<<<grid, block, 0, s>>>(args...), with the launch timed by ev when ev is given.
+template <typename... Params, typename... Args>
+inline void launch_timed(void (*kernel)(Params...), int grid, int block, hipStream_t s, const LaunchEvents *ev,
+                         Args... args) {
+  if (ev)
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, ev->start, ev->stop, 0, Params(args)...);
+  else
+    kernel<<<grid, block, 0, s>>>(Params(args)...);
 }
 
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }

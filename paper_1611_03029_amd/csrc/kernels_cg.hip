@@ -877,30 +877,36 @@ hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, con
 
 template <int K, typename T>
 static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, T> &tab, const T *kappa,
-                             const T *metric, const T *src, T *dst, T *halo, hipStream_t s, int dmask) {
+                             const T *metric, const T *src, T *dst, T *halo, hipStream_t s, int dmask,
+                             const LaunchEvents *ev) {
   const int dm = dmask < 0 ? dirichlet_mask(c.p) : dmask;
   (void)tab;
+  const T *none = nullptr;
   if (c.p.geometry == MFL_GEOM_CURVED) {
     const BrickGrid bg = brick_grid<K, T, true, kShapeDefault>(L.Nc, L.N1, dm);
-    apply_brick_kernel<K, T, true, kShapeDefault><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, metric, bg, T(L.h));
+    launch_timed(apply_brick_kernel<K, T, true, kShapeDefault>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src, dst,
+                 halo, kappa, metric, bg, T(L.h));
   } else {
     const int shape = level_shape<K, T, false>(L.Nc);
     if constexpr (TallShape<K, T, false>::tall) {
       if (shape == kShapeTall) {
         const BrickGrid bg = brick_grid<K, T, false, kShapeTall>(L.Nc, L.N1, dm);
-        apply_brick_kernel<K, T, false, kShapeTall><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+        launch_timed(apply_brick_kernel<K, T, false, kShapeTall>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src,
+                     dst, halo, kappa, none, bg, T(L.h));
         return hipGetLastError();
       }
     }
     if constexpr (kHasShort<K>) {
       if (shape == kShapeShort) {
         const BrickGrid bg = brick_grid<K, T, false, kShapeShort>(L.Nc, L.N1, dm);
-        apply_brick_kernel<K, T, false, kShapeShort><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+        launch_timed(apply_brick_kernel<K, T, false, kShapeShort>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src,
+                     dst, halo, kappa, none, bg, T(L.h));
         return hipGetLastError();
       }
     }
     const BrickGrid bg = brick_grid<K, T, false, kShapeDefault>(L.Nc, L.N1, dm);
-    apply_brick_kernel<K, T, false, kShapeDefault><<<bg.nbx * bg.nby * bg.nbz, kBlock, 0, s>>>(src, dst, halo, kappa, nullptr, bg, T(L.h));
+    launch_timed(apply_brick_kernel<K, T, false, kShapeDefault>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src,
+                 dst, halo, kappa, none, bg, T(L.h));
   }
   return hipGetLastError();
 }
@@ -1094,13 +1100,13 @@ hipError_t launch_cg_cheb_halo(const Context &c, const Level &L, const void *b, 
 }
 
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
-                           hipStream_t s, int dmask) {
+                           hipStream_t s, int dmask, const LaunchEvents *ev) {
   if (dtype == MFL_F64) {
-#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s, dmask)
+#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s, dmask, ev)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   } else {
-#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s, dmask)
+#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s, dmask, ev)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }

@@ -309,13 +309,12 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
 }
 
 template <int K, typename T>
-hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStream_t s) {
+hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStream_t s, const LaunchEvents *ev) {
   constexpr int CPB = DGLanes<K>::cpb;
   const int grid = 8 * ColumnOrder::blocks_per_xcd(L.Nc, CPB);
   const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
   if (!xline_aligned<K>({src, dst})) return hipErrorInvalidValue;
-  sipg_kernel<K, T><<<grid, kBlock, 0, s>>>(src, dst, L.Nc, T(L.h), T(sigma),
-                                           dirichlet_mask(c.p));
+  launch_timed(sipg_kernel<K, T>, grid, kBlock, s, ev, src, dst, L.Nc, T(L.h), T(sigma), dirichlet_mask(c.p));
   return hipGetLastError();
 }
 
@@ -787,13 +786,13 @@ inline int grid_for(int64_t items, int cap = 16384) {
 }  // namespace
 
 hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
-                             hipStream_t s) {
+                             hipStream_t s, const LaunchEvents *ev) {
   if (dtype == MFL_F64) {
-#define CASE(K) return sipg_k<K, double>(c, L, (const double *)src, (double *)dst, s)
+#define CASE(K) return sipg_k<K, double>(c, L, (const double *)src, (double *)dst, s, ev)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   } else {
-#define CASE(K) return sipg_k<K, float>(c, L, (const float *)src, (float *)dst, s)
+#define CASE(K) return sipg_k<K, float>(c, L, (const float *)src, (float *)dst, s, ev)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }

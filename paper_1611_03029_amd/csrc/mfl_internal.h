@@ -102,6 +102,8 @@ struct Level {
   // multigrid vectors in the cycle's precision (FP64 on the coarsest level)
   void *b = nullptr, *x = nullptr, *ax = nullptr, *d = nullptr;
   void *x2 = nullptr;           // SIPG with the GLL Jacobi smoother: the fused step's second x
+  void *tbuf = nullptr;         // CG multigrid, level >= 1: transfer intermediate, N1 N1c^2
+                                // values (N1c of the next coarser level), FP64 size
   bool mg_f32 = false;          // vectors of this level are float
   double lambda_max = 0.0;
   double coarse_lmin = 0.0, coarse_lmax = 0.0;
@@ -150,6 +152,12 @@ void gauss_lobatto(int n, double *x, double *w);
 void lagrange_eval(int n, const double *nodes, double x, double *val, double *der);
 void build_tables(int k, Tab<kMaxN, double> &t64, Tab<kMaxN, float> &t32, TransferTab &tt);
 
+// Optional timing of one kernel launch: the dispatch packet itself records start and stop
+// (hipExtLaunchKernelGGL), so timing adds no packets between kernels.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // ---- kernel launchers (return hipError_t of the launch) -----------------------
 hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, const void *src,
                                 void *dst, hipStream_t s);
@@ -157,7 +165,7 @@ hipError_t launch_boundary_init(const Context &c, const Level &L, int dtype, con
 // (dmask < 0: the Dirichlet faces of the parameters; 0: the operator without boundary
 // conditions, used for the lifting of Dirichlet data)
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
-                           hipStream_t s, int dmask = -1);
+                           hipStream_t s, int dmask = -1, const LaunchEvents *ev = nullptr);
 hipError_t launch_cg_halo_add(const Context &c, const Level &L, int dtype, void *dst, hipStream_t s,
                               int dmask = -1);
 int64_t cg_halo_elements(int k, int Nc, bool curved);
@@ -178,7 +186,7 @@ hipError_t launch_gaussian_dirichlet(const Context &c, const Level &L, double *x
 hipError_t launch_lift(const Context &c, const Level &L, double *b, const double *x0, const double *a0,
                        hipStream_t s);
 hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
-                             hipStream_t s);
+                             hipStream_t s, const LaunchEvents *ev = nullptr);
 // SIPG: matrix diagonal (FP64, then inverse and FP32 copies), embedding transfers between
 // level `coarse` and the next finer one, and the right-hand side of the three-Gaussian example
 hipError_t launch_sipg_diagonal(const Context &c, const Level &L, hipStream_t s);
