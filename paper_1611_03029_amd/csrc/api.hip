@@ -166,10 +166,7 @@ int64_t layout(Context &c, char *base) {
       L.ax = b.take<char>(L.ndofs * es);
       L.d = b.take<char>(L.ndofs * es);
       if (p.disc == MFL_DISC_SIPG && p.dg_jacobi_basis == MFL_DG_JACOBI_GLL) L.x2 = b.take<char>(L.ndofs * es);
-      if (cg && l > 0) {
-        const int64_t N1c = c.levels[l - 1].N1;
-        L.tbuf = b.take<double>(int64_t(L.N1) * N1c * N1c);
-      }
+      if (cg && l > 0) L.tbuf = b.take<double>(c.levels[l - 1].ncells * n3);
     }
   }
   {

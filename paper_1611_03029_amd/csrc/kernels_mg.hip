@@ -115,185 +115,157 @@ cheb_step_kernel(const T *__restrict__ b, const T *__restrict__ ax, const T *__r
   }
 }
 
-// ---- transfers between continuous Q_k levels (Sec. 4.1) ------------------------------
-// Prolongation is the embedding P = P1 (x) P1 (x) P1 of the coarse Q_k space in the fine one,
-// restriction its transpose, both with the rows and columns of Dirichlet DoFs removed.  P1 is
-// applied as a gather, so that every output value is written once (no atomics, no clearing
-// pass) and every pass streams whole rows: restriction in x and y per fine z-plane, then in
-// z; prolongation in z, then in x and y per fine z-plane.  T holds the intermediate
-// [fine z][coarse y][coarse x] (N1f N1c^2 values).
-//
-// 1D embedding: fine line f lies in fine cell min(f / K, Nf - 1), whose coarse parent is
-// pc = that / 2, at the fl = f - 2K pc -th of the 2K+1 fine lines of pc, so
-// P1[f][I] = P[fl][I - K pc] (the coarse basis of pc at that line) when 0 <= I - K pc <= K and
-// 0 otherwise.  The fine lines where coarse line I = K c + a is nonzero lie in
-// [2I - 2K, 2I + 2K] (in [2K c, 2K (c+1)] for 0 < a < K, plus cell c - 1 for a = 0).
-template <int K>
-__device__ __forceinline__ int embed_parent(int f, int Nf) {
-  return min(f / K, Nf - 1) / 2;
-}
-
-template <int K>
-__device__ __forceinline__ double embed_weight(const double *P, int Nf, int f, int I) {
-  const int pc = embed_parent<K>(f, Nf), a = I - K * pc;
-  return (a >= 0 && a <= K) ? P[(f - 2 * K * pc) * (K + 1) + a] : 0.0;
-}
-
-constexpr int kRestrictTX = 32, kRestrictTY = 16;   // coarse x, y DoFs of a restriction tile
-constexpr int kProlongTX = 64, kProlongTY = 16;     // fine x, y DoFs of a prolongation tile
-
-// T[fz][J][I] = sum_{fy, fx} P1[fy][J] P1[fx][I] r[fz][fy][fx] with r = b_f - A x_f (axf ==
-// nullptr: r = b_f), zero on Dirichlet DoFs.  Work-group = one tile of kRestrictTX x
-// kRestrictTY coarse (x, y) DoFs of one fine z-plane (blockIdx.y): the x sums of the fine
-// rows the tile needs go to LDS, then the y sums to T.
-template <int K, typename TF>
-__global__ void __launch_bounds__(kBlock)
-restrict_xy_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TF *__restrict__ T, int Ncc, int dmask,
-                   TransferTab tt) {
-  constexpr int n = K + 1, TX = kRestrictTX, TY = kRestrictTY, FY = 2 * TY + 4 * K - 1;
-  __shared__ double P[(2 * K + 1) * n];
-  __shared__ TF U[FY * TX];
-  for (int i = threadIdx.x; i < (2 * K + 1) * n; i += kBlock) P[i] = tt.P[i];
-  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1, Nf = 2 * Ncc;
-  const int ntx = (N1c + TX - 1) / TX;
-  const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx, fz = int(blockIdx.y);
-  const int I0 = tx * TX, J0 = ty * TY, fy0 = 2 * J0 - 2 * K;
-  const bool zbnd = on_dirichlet(fz, N1f, dmask);
-  const int64_t plane = int64_t(fz) * N1f * N1f;
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < FY * TX; idx += kBlock) {
-    const int r = idx / TX, i = idx - r * TX, I = I0 + i, fy = fy0 + r;
-    TF acc = 0;
-    if (!zbnd && I < N1c && fy >= 0 && fy < N1f && !on_dirichlet(fy, N1f, dmask)) {
-      const int64_t row = plane + int64_t(fy) * N1f;
-#pragma unroll
-      for (int d = -2 * K; d <= 2 * K; ++d) {
-        const int f = 2 * I + d;
-        if (f < 0 || f >= N1f || on_dirichlet(f, N1f, dmask)) continue;
-        const double w = embed_weight<K>(P, Nf, f, I);
-        if (w != 0.0) acc += TF(w) * (axf ? bf[row + f] - axf[row + f] : bf[row + f]);
-      }
-    }
-    U[idx] = acc;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < TY * TX; idx += kBlock) {
-    const int j = idx / TX, i = idx - j * TX, I = I0 + i, J = J0 + j;
-    if (I >= N1c || J >= N1c) continue;
-    TF acc = 0;
-#pragma unroll
-    for (int d = -2 * K; d <= 2 * K; ++d) {
-      const int fy = 2 * J + d;
-      if (fy < 0 || fy >= N1f) continue;
-      acc += TF(embed_weight<K>(P, Nf, fy, J)) * U[(fy - fy0) * TX + i];
-    }
-    T[(int64_t(fz) * N1c + J) * N1c + I] = acc;
-  }
-}
-
-// bc[Iz][J][I] = sum_fz P1[fz][Iz] T[fz][J][I]; zero on the coarse Dirichlet DoFs.
-template <int K, typename TF, typename TC>
-__global__ void __launch_bounds__(kBlock)
-restrict_z_kernel(const TF *__restrict__ T, TC *__restrict__ bc, int Ncc, int dmask, TransferTab tt) {
-  constexpr int n = K + 1;
-  __shared__ double P[(2 * K + 1) * n];
-  for (int i = threadIdx.x; i < (2 * K + 1) * n; i += kBlock) P[i] = tt.P[i];
-  __syncthreads();
-  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1, Nf = 2 * Ncc;
-  const int64_t pc2 = int64_t(N1c) * N1c, total = pc2 * N1c;
-  GRID_STRIDE(idx, total) {
-    const int I = int(idx % N1c), J = int((idx / N1c) % N1c), Iz = int(idx / pc2);
-    TF acc = 0;
-    if (!dirichlet_dof(I, J, Iz, N1c, dmask)) {
-      const int64_t col = int64_t(J) * N1c + I;
-#pragma unroll
-      for (int d = -2 * K; d <= 2 * K; ++d) {
-        const int fz = 2 * Iz + d;
-        if (fz < 0 || fz >= N1f) continue;
-        const double w = embed_weight<K>(P, Nf, fz, Iz);
-        if (w != 0.0) acc += TF(w) * T[int64_t(fz) * pc2 + col];
-      }
-    }
-    bc[idx] = TC(acc);
-  }
-}
-
-// T[fz][J][I] = sum_Iz P1[fz][Iz] xc[Iz][J][I] (coarse Dirichlet DoFs taken as zero).
+// fine += P coarse over one coarse cell per work-group: embedding of the coarse Q_k
+// basis at the (2k+1)^3 fine nodes, applied direction by direction.  Each fine node is
+// written by exactly one coarse cell (half-open ownership), so no atomics are needed.
+// A coarse cell covers only 2k fine DoFs of each fine row, so neighbouring cells in x share
+// the fine rows' cache lines: the blocks of one XCD take consecutive cells (xcd_block), so
+// that those lines are reused in that XCD's L2 instead of being fetched by several XCDs.
 template <int K, typename TC, typename TF>
 __global__ void __launch_bounds__(kBlock)
-prolong_z_kernel(const TC *__restrict__ xc, TF *__restrict__ T, int Ncc, int dmask, TransferTab tt) {
-  constexpr int n = K + 1;
-  __shared__ double P[(2 * K + 1) * n];
-  for (int i = threadIdx.x; i < (2 * K + 1) * n; i += kBlock) P[i] = tt.P[i];
+prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int dmask, TransferTab tt) {
+  constexpr int n = K + 1, m = 2 * K + 1;
+  constexpr int s0 = (n * n * n > m * m * n) ? n * n * n : m * m * n;
+  __shared__ double P[m * n];
+  __shared__ TF b0[s0], b1[m * n * n];
+  for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
+  const int64_t cell = xcd_block(blockIdx.x, gridDim.x);
+  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
+  for (int i = threadIdx.x; i < n * n * n; i += kBlock) {
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
+    const bool bnd = dirichlet_dof(gx, gy, gz, N1c, dmask);
+    b0[i] = bnd ? TF(0) : TF(xc[gx + int64_t(N1c) * (gy + int64_t(N1c) * gz)]);
+  }
   __syncthreads();
-  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1, Nf = 2 * Ncc;
-  const int64_t pc2 = int64_t(N1c) * N1c, total = pc2 * N1f;
-  GRID_STRIDE(idx, total) {
-    const int I = int(idx % N1c), J = int((idx / N1c) % N1c), fz = int(idx / pc2);
-    TF acc = 0;
-    if (!on_dirichlet(I, N1c, dmask) && !on_dirichlet(J, N1c, dmask)) {
-      const int pc = embed_parent<K>(fz, Nf), fl = fz - 2 * K * pc;
-#pragma unroll
-      for (int a = 0; a <= K; ++a) {
-        const int Iz = K * pc + a;
-        if (on_dirichlet(Iz, N1c, dmask)) continue;
-        acc += TF(P[fl * n + a]) * TF(xc[int64_t(Iz) * pc2 + int64_t(J) * N1c + I]);
-      }
-    }
-    T[idx] = acc;
+  for (int i = threadIdx.x; i < m * n * n; i += kBlock) {   // z: [L][j][i]
+    const int a = i % n, b = (i / n) % n, L = i / (n * n);
+    TF s = 0;
+    for (int l = 0; l < n; ++l) s += TF(P[L * n + l]) * b0[l * n * n + b * n + a];
+    b1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m * n; i += kBlock) {   // y: [L][J][i]
+    const int a = i % n, J = (i / n) % m, L = i / (n * m);
+    TF s = 0;
+    for (int b = 0; b < n; ++b) s += TF(P[J * n + b]) * b1[L * n * n + b * n + a];
+    b0[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m * m; i += kBlock) {   // x: fine node (I, J, L)
+    const int I = i % m, J = (i / m) % m, L = i / (m * m);
+    if ((I == m - 1 && cx < Ncc - 1) || (J == m - 1 && cy < Ncc - 1) || (L == m - 1 && cz < Ncc - 1))
+      continue;                                             // owned by the next coarse cell
+    const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
+    if (dirichlet_dof(fx, fy, fz, N1f, dmask)) continue;
+    TF s = 0;
+    for (int a = 0; a < n; ++a) s += TF(P[I * n + a]) * b0[L * m * n + J * n + a];
+    xf[fx + int64_t(N1f) * (fy + int64_t(N1f) * fz)] += s;
   }
 }
 
-// xf[fz][fy][fx] += sum_{J, I} P1[fy][J] P1[fx][I] T[fz][J][I] on the non-Dirichlet fine DoFs.
-// Work-group = one tile of kProlongTX x kProlongTY fine (x, y) DoFs of one fine z-plane: the
-// coarse (x, y) block of T the tile needs goes to LDS, then its x sums, then the y sums are
-// added to xf.
+// Restriction coarse = P^T (b_f - A x_f) (axf == nullptr: P^T b_f) in two kernels without
+// atomics.  restrict_cell_kernel: one coarse cell per work-group applies the transposed
+// embedding to the (2k+1)^3 fine values of the cell, fine nodes shared by several coarse
+// cells weighted by 1/multiplicity so that the sum over cells is P^T, and stores the cell's
+// n^3 contributions contiguously in `cellbuf` (block order as in prolongate_kernel:
+// consecutive cells on one XCD share the fine rows' cache lines).  restrict_gather_kernel:
+// each coarse DoF sums the contributions of the 1 to 8 cells that contain it, in a fixed
+// order, and is written once (zero on Dirichlet DoFs).
 template <int K, typename TF>
 __global__ void __launch_bounds__(kBlock)
-prolong_xy_kernel(const TF *__restrict__ T, TF *__restrict__ xf, int Ncc, int dmask, TransferTab tt) {
-  constexpr int n = K + 1, FX = kProlongTX, FYT = kProlongTY;
-  // coarse lines a tile of F fine lines touches: K (parent(last) - parent(first)) + K + 1 <=
-  // F / 2 + 2K + 1 (parents of lines F - 1 apart differ by at most (F - 1) / (2K) + 1)
-  constexpr int CX = FX / 2 + 2 * K + 2, CY = FYT / 2 + 2 * K + 2;
-  __shared__ double P[(2 * K + 1) * n];
-  __shared__ TF Tc[CY * CX];
-  __shared__ TF V[CY * FX];
-  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1, Nf = 2 * Ncc;
-  const int fz = int(blockIdx.y);
-  if (on_dirichlet(fz, N1f, dmask)) return;   // the same for the whole work-group
-  for (int i = threadIdx.x; i < (2 * K + 1) * n; i += kBlock) P[i] = tt.P[i];
-  const int ntx = (N1f + FX - 1) / FX;
-  const int fx0 = (int(blockIdx.x) % ntx) * FX, fy0 = (int(blockIdx.x) / ntx) * FYT;
-  const int fx1 = min(fx0 + FX, N1f) - 1, fy1 = min(fy0 + FYT, N1f) - 1;
-  const int cx0 = K * embed_parent<K>(fx0, Nf), cy0 = K * embed_parent<K>(fy0, Nf);
-  const int wx = K * embed_parent<K>(fx1, Nf) + K + 1 - cx0, wy = K * embed_parent<K>(fy1, Nf) + K + 1 - cy0;
-  const int64_t tplane = int64_t(fz) * N1c * N1c;
-  for (int idx = threadIdx.x; idx < wy * wx; idx += kBlock) {
-    const int cy = idx / wx, cx = idx - cy * wx;
-    Tc[cy * CX + cx] = T[tplane + int64_t(cy0 + cy) * N1c + cx0 + cx];
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < wy * FX; idx += kBlock) {
-    const int cy = idx / FX, i = idx - cy * FX, fx = fx0 + i;
-    TF acc = 0;
-    if (fx < N1f) {
-      const int pc = embed_parent<K>(fx, Nf), fl = fx - 2 * K * pc, o = K * pc - cx0;
-#pragma unroll
-      for (int a = 0; a <= K; ++a) acc += TF(P[fl * n + a]) * Tc[cy * CX + o + a];
+restrict_cell_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TF *__restrict__ cellbuf, int Ncc,
+                     int dmask, TransferTab tt) {
+  constexpr int n = K + 1, m = 2 * K + 1;
+  __shared__ double P[m * n];
+  __shared__ TF r[m * m * m], t1[m * m * n];
+  for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
+  const int64_t cell = xcd_block(blockIdx.x, gridDim.x);
+  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
+  for (int i = threadIdx.x; i < m * m * m; i += kBlock) {
+    const int I = i % m, J = (i / m) % m, L = i / (m * m);
+    const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
+    TF v = 0;
+    if (!dirichlet_dof(fx, fy, fz, N1f, dmask)) {
+      const int64_t g = fx + int64_t(N1f) * (fy + int64_t(N1f) * fz);
+      TF wgt = 1;
+      if ((I == 0 && cx > 0) || (I == m - 1 && cx < Ncc - 1)) wgt *= TF(0.5);
+      if ((J == 0 && cy > 0) || (J == m - 1 && cy < Ncc - 1)) wgt *= TF(0.5);
+      if ((L == 0 && cz > 0) || (L == m - 1 && cz < Ncc - 1)) wgt *= TF(0.5);
+      v = wgt * (axf ? bf[g] - axf[g] : bf[g]);
     }
-    V[cy * FX + i] = acc;
+    r[i] = v;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < FYT * FX; idx += kBlock) {
-    const int j = idx / FX, i = idx - j * FX, fx = fx0 + i, fy = fy0 + j;
-    if (fx >= N1f || fy >= N1f || on_dirichlet(fx, N1f, dmask) || on_dirichlet(fy, N1f, dmask)) continue;
-    const int pc = embed_parent<K>(fy, Nf), fl = fy - 2 * K * pc, o = K * pc - cy0;
-    TF acc = 0;
-#pragma unroll
-    for (int b = 0; b <= K; ++b) acc += TF(P[fl * n + b]) * V[(o + b) * FX + i];
-    xf[(int64_t(fz) * N1f + fy) * N1f + fx] += acc;
+  for (int i = threadIdx.x; i < m * m * n; i += kBlock) {   // x: [L][J][a]
+    const int a = i % n, J = (i / n) % m, L = i / (n * m);
+    TF s = 0;
+    for (int I = 0; I < m; ++I) s += TF(P[I * n + a]) * r[L * m * m + J * m + I];
+    t1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * n * n; i += kBlock) {   // y: [L][b][a] (reuses r)
+    const int a = i % n, b = (i / n) % n, L = i / (n * n);
+    TF s = 0;
+    for (int J = 0; J < m; ++J) s += TF(P[J * n + b]) * t1[L * m * n + J * n + a];
+    r[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * n * n; i += kBlock) {   // z: coarse DoF (a, b, l)
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    TF s = 0;
+    for (int L = 0; L < m; ++L) s += TF(P[L * n + l]) * r[L * n * n + b * n + a];
+    cellbuf[cell * (n * n * n) + i] = s;
   }
 }
+
+// Cells containing coarse grid line g of Nc cells along one direction, with the line's
+// local index in each: (g / K, g % K) inside a cell; at a cell vertex also (g / K - 1, K);
+// the last line only in the last cell.  Returns the count (1 or 2).
+template <int K>
+__device__ __forceinline__ int line_cells(int g, int Nc, int (&c)[2], int (&a)[2]) {
+  const int q = g / K, r = g - q * K;
+  if (q == Nc) {
+    c[0] = Nc - 1;
+    a[0] = K;
+    return 1;
+  }
+  c[0] = q;
+  a[0] = r;
+  if (r == 0 && q > 0) {
+    c[1] = q - 1;
+    a[1] = K;
+    return 2;
+  }
+  return 1;
+}
+
+template <int K, typename TF, typename TC>
+__global__ void __launch_bounds__(kBlock)
+restrict_gather_kernel(const TF *__restrict__ cellbuf, TC *__restrict__ bc, int Ncc, int dmask) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  const int N1c = K * Ncc + 1;
+  const int64_t total = int64_t(N1c) * N1c * N1c;
+  GRID_STRIDE(i, total) {
+    const int gx = int(i % N1c), gy = int((i / N1c) % N1c), gz = int(i / (int64_t(N1c) * N1c));
+    TF s = 0;
+    if (!dirichlet_dof(gx, gy, gz, N1c, dmask)) {
+      int cx[2], ax[2], cy[2], ay[2], cz[2], az[2];
+      const int nx = line_cells<K>(gx, Ncc, cx, ax), ny = line_cells<K>(gy, Ncc, cy, ay),
+                nz = line_cells<K>(gz, Ncc, cz, az);
+      for (int tz = 0; tz < nz; ++tz)
+        for (int ty = 0; ty < ny; ++ty)
+          for (int tx = 0; tx < nx; ++tx) {
+            const int64_t cell = cx[tx] + int64_t(Ncc) * (cy[ty] + int64_t(Ncc) * cz[tz]);
+            s += cellbuf[cell * n3 + ax[tx] + n * (ay[ty] + n * az[tz])];
+          }
+    }
+    bc[i] = TC(s);
+  }
+}
+
 
 __global__ void __launch_bounds__(kBlock)
 dot_partial_kernel(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
@@ -461,33 +433,25 @@ hipError_t launch_cheb_step(const void *b, const void *ax, const void *dinv, voi
   return hipGetLastError();
 }
 
-template <int K, typename TC, typename TF>
-static hipError_t prolongate_kt(const Context &c, const Level &coarse, const Level &fine, const void *xc, void *xf,
-                                hipStream_t s) {
-  const int N1c = coarse.N1, N1f = fine.N1;
-  TF *T = static_cast<TF *>(fine.tbuf);
-  const int64_t nt = int64_t(N1f) * N1c * N1c;
-  prolong_z_kernel<K, TC, TF><<<grid_for(nt), kBlock, 0, s>>>((const TC *)xc, T, coarse.Nc, dirichlet_mask(c.p),
-                                                             c.transfer);
-  const int tiles = ((N1f + kProlongTX - 1) / kProlongTX) * ((N1f + kProlongTY - 1) / kProlongTY);
-  prolong_xy_kernel<K, TF><<<dim3(tiles, N1f), kBlock, 0, s>>>(T, (TF *)xf, coarse.Nc, dirichlet_mask(c.p),
-                                                               c.transfer);
-  return hipGetLastError();
-}
-
 template <int K>
-static hipError_t prolongate_k(const Context &c, const Level &coarse, const Level &fine, const void *xc, int cd,
+static hipError_t prolongate_k(const Context &c, const Level &coarse, const void *xc, int cd,
                                void *xf, int fd, hipStream_t s) {
-  if (fd == MFL_F64 && cd == MFL_F64) return prolongate_kt<K, double, double>(c, coarse, fine, xc, xf, s);
-  if (fd == MFL_F32 && cd == MFL_F64) return prolongate_kt<K, double, float>(c, coarse, fine, xc, xf, s);
-  if (fd == MFL_F32 && cd == MFL_F32) return prolongate_kt<K, float, float>(c, coarse, fine, xc, xf, s);
-  return hipErrorInvalidValue;
+  const int grid = int(coarse.ncells);
+  if (cd == MFL_F64 && fd == MFL_F64)
+    prolongate_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)xc, (double *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
+  else if (cd == MFL_F64 && fd == MFL_F32)
+    prolongate_kernel<K, double, float><<<grid, kBlock, 0, s>>>((const double *)xc, (float *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
+  else if (cd == MFL_F32 && fd == MFL_F32)
+    prolongate_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)xc, (float *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_prolongate_add(const Context &c, const Level &coarse, const Level &fine,
                                  const void *xc, int cd, void *xf, int fd, hipStream_t s) {
-  if (!fine.tbuf) return hipErrorInvalidValue;
-#define CASE(K) return prolongate_k<K>(c, coarse, fine, xc, cd, xf, fd, s)
+  (void)fine;
+#define CASE(K) return prolongate_k<K>(c, coarse, xc, cd, xf, fd, s)
   MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   return hipErrorInvalidValue;
@@ -496,13 +460,11 @@ hipError_t launch_prolongate_add(const Context &c, const Level &coarse, const Le
 template <int K, typename TF, typename TC>
 static hipError_t restrict_kt(const Context &c, const Level &coarse, const Level &fine, const void *bf,
                               const void *axf, void *bc, hipStream_t s) {
-  const int N1c = coarse.N1, N1f = fine.N1;
-  TF *T = static_cast<TF *>(fine.tbuf);
-  const int tiles = ((N1c + kRestrictTX - 1) / kRestrictTX) * ((N1c + kRestrictTY - 1) / kRestrictTY);
-  restrict_xy_kernel<K, TF><<<dim3(tiles, N1f), kBlock, 0, s>>>((const TF *)bf, (const TF *)axf, T, coarse.Nc,
-                                                                dirichlet_mask(c.p), c.transfer);
-  restrict_z_kernel<K, TF, TC><<<grid_for(coarse.ndofs), kBlock, 0, s>>>(T, (TC *)bc, coarse.Nc,
-                                                                         dirichlet_mask(c.p), c.transfer);
+  TF *cellbuf = static_cast<TF *>(fine.tbuf);
+  restrict_cell_kernel<K, TF><<<int(coarse.ncells), kBlock, 0, s>>>((const TF *)bf, (const TF *)axf, cellbuf,
+                                                                    coarse.Nc, dirichlet_mask(c.p), c.transfer);
+  restrict_gather_kernel<K, TF, TC><<<grid_for(coarse.ndofs), kBlock, 0, s>>>(cellbuf, (TC *)bc, coarse.Nc,
+                                                                              dirichlet_mask(c.p));
   return hipGetLastError();
 }
 

@@ -36,6 +36,20 @@ struct DGLanes {
   static constexpr int cpb = wave ? (kBlock / 64) * (64 / n2) : kBlock / n2;   // cells per block
 };
 
+// LDS layout of a cell's n^3 values in the operator kernel: point (x, y, z) at z PS + y n + x
+// of the cell's block of CS values.  The padded plane and cell strides spread the lanes of a
+// phase over the LDS banks: with the unpadded strides n^2 and n^3 (powers of two for odd k)
+// the lanes of the cells of one wavefront that read the same point of their cells hit the
+// same bank (measured 11.4 conflict cycles per LDS instruction at k = 3).  Chosen with a
+// model of 64 four-byte banks serving 32 lanes per cycle; k = 2, 4, 8 need no padding.
+template <int K>
+struct DGLds {
+  static constexpr int n = K + 1;
+  static constexpr int pp = K == 1 ? 2 : K == 3 ? 3 : K == 5 ? 1 : K == 6 ? 3 : K == 7 ? 5 : 0;
+  static constexpr int cp = K == 3 ? 4 : K == 5 ? 6 : K == 6 ? 5 : 0;
+  static constexpr int PS = n * n + pp, CS = n * PS + cp;
+};
+
 // out = scale * A1-part of one line: the cell term K_g u / h plus the two faces of the cell
 // along this direction (face 0 at xi = 0 with outward normal -1, face 1 at xi = 1 with +1).
 // Per face, with own and neighbour end-point values v-, v+ and derivatives d-, d+:
@@ -233,9 +247,10 @@ template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
 sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma, int dmask) {
   constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = DGLanes<K>::cpb;
+  constexpr int PS = DGLds<K>::PS, CS = DGLds<K>::CS;
   constexpr bool WL = DGLanes<K>::wave;
   constexpr const ct::DGTab<n, T> &tb = ct::DGTables<n, T>::tab;
-  __shared__ T U[CPB * n3], R[CPB * n3];
+  __shared__ T U[CPB * CS], R[CPB * CS];
   const LaneMap<n2, WL> lm(threadIdx.x, CPB);
   const int lc = lm.slot, p = lm.p, i0 = p % n, i1 = p / n;
   const bool inblk = lm.used;
@@ -245,7 +260,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
   const T inv_h = T(1) / h;
   const T scale = h * h * tb.w[i0] * tb.w[i1];   // tangential weights of every phase
   const int slot = inblk ? lc : 0;
-  T *Uc = U + slot * n3, *Rc = R + slot * n3;
+  T *Uc = U + slot * CS, *Rc = R + slot * CS;
   const T *uc = src + cell * n3;
   const int64_t plane = int64_t(Nc) * Nc;
   // Loads are unconditional: every pointer below addresses a cell of src (an inactive lane
@@ -266,8 +281,8 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-      Uc[l * n2 + p] = u[l];
-      Rc[l * n2 + p] = out[l];
+      Uc[l * PS + p] = u[l];
+      Rc[l * PS + p] = out[l];
     }
   }
   cell_sync<WL>();
@@ -279,30 +294,30 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
 #pragma unroll
     for (int b = 0; b < n; ++b) {
       const int o = i1 * n2 + b * n + i0;
-      u[b] = Uc[o];
+      u[b] = Uc[i1 * PS + b * n + i0];
       ul[b] = pl[o];
       ur[b] = pr[o];
     }
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
 #pragma unroll
-    for (int b = 0; b < n; ++b) Rc[i1 * n2 + b * n + i0] += out[b];
+    for (int b = 0; b < n; ++b) Rc[i1 * PS + b * n + i0] += out[b];
   }
   cell_sync<WL>();
   // phase x: lanes own x-lines (y = i0, z = i1); the sum of the three directions is stored
   if (inblk) {
     T u[n], ul[n], ur[n], out[n];
     const bool hasL = cx > 0, hasR = cx < Nc - 1;
-    const int o = i1 * n2 + i0 * n;
+    const int o = i1 * n2 + i0 * n, ol = i1 * PS + i0 * n;
     const T *pl = src + (hasL ? cell - 1 : cell) * n3 + o, *pr = src + (hasR ? cell + 1 : cell) * n3 + o;
     constexpr bool VX = sizeof(T) == 8;
     load_xline<n, VX>(pl, ul);
     load_xline<n, VX>(pr, ur);
 #pragma unroll
-    for (int a = 0; a < n; ++a) u[a] = Uc[o + a];
+    for (int a = 0; a < n; ++a) u[a] = Uc[ol + a];
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
     if (active) {
 #pragma unroll
-      for (int a = 0; a < n; ++a) out[a] += Rc[o + a];
+      for (int a = 0; a < n; ++a) out[a] += Rc[ol + a];
       store_xline<n, VX>(dst + cell * n3 + o, out);
     }
   }

@@ -102,8 +102,9 @@ struct Level {
   // multigrid vectors in the cycle's precision (FP64 on the coarsest level)
   void *b = nullptr, *x = nullptr, *ax = nullptr, *d = nullptr;
   void *x2 = nullptr;           // SIPG with the GLL Jacobi smoother: the fused step's second x
-  void *tbuf = nullptr;         // CG multigrid, level >= 1: transfer intermediate, N1 N1c^2
-                                // values (N1c of the next coarser level), FP64 size
+  void *tbuf = nullptr;         // CG multigrid, level >= 1: the restriction's per-cell
+                                // contributions, (k+1)^3 values per cell of the next coarser
+                                // level, FP64 size
   bool mg_f32 = false;          // vectors of this level are float
   double lambda_max = 0.0;
   double coarse_lmin = 0.0, coarse_lmax = 0.0;
