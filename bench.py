@@ -120,6 +120,32 @@ def repetitions(prob, src, dst, reps=20, per_rep=10):
     return {"reps": reps, "applies_per_rep": per_rep, "min_ms": times[0], "median_ms": times[reps // 2]}
 
 
+def hbm_ceilings(nbytes=1 << 30, reps=10):
+    """Practical HBM rates on this GPU with library kernels: a streaming read (sum of a
+    float64 tensor of nbytes) and a device copy of nbytes; best of `reps`, GB/s."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, moved in (("read_GBs", lambda: a.sum(), nbytes), ("copy_GBs", lambda: b.copy_(a), 2 * nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        out[name] = moved / (best * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out["bytes"] = nbytes
+    return out
+
+
 def calibration_copy(n):
     """A plain device copy of n doubles (the reference kernel for counter scaling)."""
     import torch
@@ -710,6 +736,7 @@ def main():
     calib = calibration_copy(n)
     del u64
     torch.cuda.empty_cache()
+    ceilings = hbm_ceilings()
 
     result = {
         "metric": METRIC,
@@ -734,7 +761,8 @@ def main():
                      "algorithmic_bytes": bytes64, "timed_launches": launches,
                      "kernel_source_hash": kernel_source_hash(),
                      "step_frac": bytes64 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "step_frac_protocol_min": bytes64 / (protocol["min_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "step_frac_protocol_min": bytes64 / (protocol["min_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "hbm_ceilings_measured": ceilings},
         "equiv_dofs_per_s": cells * k ** 3 / (ms_step * 1e-3),
         "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32,
                        "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
