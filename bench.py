@@ -252,7 +252,7 @@ PAPER_EXAMPLE_TIMES = {(2, 64): (0.1269, 5, 1.2825, 12), (3, 64): (0.4598, 5, 2.
                        (4, 64): (1.0753, 5, 5.2967, 10), (5, 48): (0.9218, 5, 4.4418, 11)}
 
 
-def paper_example(repeats=2):
+def paper_example(repeats=2, degrees=None):
     """Time to solution of the smooth-solution example (three Gaussians on (-1,1)^3, Neumann
     at x_e = -1, Dirichlet at x_e = +1) with GMG-PCG at the paper's tolerance 1e-9, CG and
     DG-SIP (penalty (k+1)^2 3/h, GLL-basis Jacobi smoother), FP32 and FP64 V-cycles."""
@@ -260,6 +260,8 @@ def paper_example(repeats=2):
     import paper_1611_03029_amd as mfl
     out = {}
     for (k, nc), (cg_s, cg_it, dg_s, dg_it) in PAPER_EXAMPLE_TIMES.items():
+        if degrees is not None and k not in degrees:
+            continue
         rec = {"cells": nc ** 3}
         for disc, name in ((mfl.CG, "cg"), (mfl.SIPG, "dg_sip")):
             for prec, pname in ((mfl.F32, "fp32_mg"), (mfl.F64, "fp64_mg")):
@@ -600,6 +602,16 @@ REDUCTIONS = {
                  "-d $R/gpurun_out/sipg_sq2 -o run -- " + _SIPG,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _TCC + " --output-format csv "
                  "-d $R/gpurun_out/sipg_tcc -o run -- " + _SIPG]},
+    "sipg_stats": {
+        "out": "profiles/sipg_apply_q3_q5_kernel_stats.txt",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+                 "-d $R/gpurun_out/sipg_ktrace -o run -- python3 $R/bench.py --sipg-only --steps 20"]},
+    "sipg_traffic": {
+        "out": "profiles/sipg_apply_q3_q5_traffic.json",
+        "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                 "-d $R/gpurun_out/sipg_fetch -o run -- " + _SIPG,
+                 "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                 "-d $R/gpurun_out/sipg_write -o run -- " + _SIPG]},
     "cg_apply_stats": {
         "out": "profiles/cg_apply_q4_64cubed_curved_kernel_stats.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
@@ -667,6 +679,18 @@ def run_reduction(name, dirs):
         for i, d in enumerate(dirs[1:]):
             summarize_sq(d, groups, "SIPG operator kernel, Q3 and Q5 on 32^3 and 64^3 cells", cmd,
                          out.replace(".txt", "_%d.txt" % (i + 2)))
+    elif name == "sipg_stats":
+        summarize_stats(dirs[0], "SIPG applies, Q3 and Q5 on 32^3 and 64^3 Cartesian cells, FP64", cmd, out)
+    elif name == "sipg_traffic":
+        kern = {}
+        for k, nc, n in ((3, 32, 32 ** 3 * 64), (3, 64, 64 ** 3 * 64), (5, 32, 32 ** 3 * 216), (5, 64, 64 ** 3 * 216)):
+            cpb = (256 // 64) * (64 // (k + 1) ** 2) if k <= 3 else 256 // (k + 1) ** 2
+            grid = 8 * (((nc // 2) * (nc // 4) * nc + cpb - 1) // cpb) * 256
+            kern["Q%d_%d^3" % (k, nc)] = {"match": "sipg_kernel<%d, double>" % k, "grid": grid,
+                                          "algorithmic_bytes": 16 * n}
+        reduce_traffic(dirs[0], dirs[1], 8 * 64 ** 3 * 216, kern, None,
+                       "SIPG applies, Q3 and Q5 on 32^3 and 64^3 Cartesian cells, FP64 (16 B/DoF algorithmic)",
+                       spec["runs"], out)
     elif name == "cg_apply_stats":
         summarize_stats(dirs[0], "CG Q4 operator, 64^3 curved cells (257^3 DoFs), FP64 and FP32 applies "
                         "(warm-up, timed and repetition-protocol applies; setup kernels once)", cmd, out)
@@ -689,6 +713,8 @@ def main():
                     help="only the SIPG applies (a profiling target; prints their JSON, not the bench line)")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the GMG-PCG solves of --solve-degrees (a profiling target; prints their JSON)")
+    ap.add_argument("--example-only", action="store_true",
+                    help="only the paper's smooth-solution example at --solve-degrees (a profiling target)")
     args = ap.parse_args()
     if args.reduce:
         run_reduction(args.reduce[0], args.reduce[1:])
@@ -704,7 +730,13 @@ def main():
 
     torch.cuda.set_device(0)
     if args.sipg_only:
-        print(json.dumps({"sipg": sipg_configs(args.steps)}), flush=True)
+        res = {"sipg": sipg_configs(args.steps)}
+        res["calibration_copy"] = calibration_copy(64 ** 3 * 216)
+        print(json.dumps(res), flush=True)
+        return
+    if args.example_only:
+        degs = [int(x) for x in args.solve_degrees.split(",") if x.strip()]
+        print(json.dumps({"paper_example": paper_example(degrees=degs)}), flush=True)
         return
     if args.solve_only:
         for d in [int(s) for s in args.solve_degrees.split(",") if s.strip()]:
