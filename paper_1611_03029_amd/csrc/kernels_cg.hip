@@ -371,12 +371,30 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T (&u)[K + 
 
 // ---------------------------------------------------------------------------------------
 // Brick apply kernel.
+
+// Raw buffer resource at p (no stride, 2^31 - 1 bytes in range, 32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brick_rsrc(const void *p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, 0x7fffffff, 0x00020000);
+}
+
+// Buffer load at byte offset voff (per lane) + soff (the same in every lane: taken from the
+// first lane, so that it is kept in a scalar register) from the resource.
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  soff = __builtin_amdgcn_readfirstlane(soff);
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 struct BrickGrid {
   int Nc, N1;
   int sx;              // cells per brick in x (multiple of the chunk width)
   int my, mz;          // brick extent in y and z in DoF intervals
   int nbx, nby, nbz;   // bricks per direction
   int dmask;           // Dirichlet face mask
+  int off32;           // per-lane offsets within a brick fit in 31 bits (see brick_grid)
 };
 
 // Halo record of a brick (upper faces owned by neighbouring bricks), M = brick extent in
@@ -447,6 +465,62 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   }
   __syncthreads();
 
+  const bool lastx = bx == bg.nbx - 1, lasty = by == bg.nby - 1, lastz = bz == bg.nbz - 1;
+  const int64_t plane = int64_t(N1) * N1;
+  const int gx0 = cx0 * K, gy0 = cy0 * K, gz0 = cz0 * K;
+  const int64_t gbase = gx0 + int64_t(N1) * gy0 + plane * gz0;
+  // interior bricks without Dirichlet DoFs and without cut-off cells need no per-item tests
+  const bool plain = gx0 + MX < N1 - 1 && gy0 + MY < N1 - 1 && gz0 + MZ < N1 - 1 &&
+                     !((bg.dmask & 1) && (gx0 == 0 || gy0 == 0 || gz0 == 0));
+
+  // Cartesian interior bricks take a walk without tests; the others the general walk.  (The
+  // same walk on curved cells, with the metric read through a buffer resource as well, was
+  // measured 4% slower at k = 4.)
+  const bool fast = !CURVED && plain && bg.off32;
+  if constexpr (!CURVED) {
+    if (fast) {
+      // Interior brick: every cell of every chunk exists and reads no Dirichlet DoF, so the
+      // walk has no per-lane tests, and each operand is read through a buffer resource at the
+      // brick (a base common to the work-group), a byte offset of the lane fixed for the whole
+      // walk and a uniform byte offset of the chunk and line.  All offsets stay below 2^31
+      // (checked on the host), so no lane does 64-bit address arithmetic.
+      const int i0 = p % n, i1 = p / n;
+      const uint32_t so = inblk ? uint32_t(sizeof(T)) * uint32_t((lx * K + i0) + N1 * (ly * K + i1) +
+                                                                 uint32_t(plane) * uint32_t(lz * K))
+                                : 0u;
+      const uint32_t ko = inblk ? uint32_t(sizeof(T)) * uint32_t(lx + Nc * (ly + Nc * lz)) : 0u;
+      const int64_t cell0 = cx0 + int64_t(Nc) * (cy0 + int64_t(Nc) * cz0);
+      const auto rs = brick_rsrc(src + gbase), rk = brick_rsrc(kappa + cell0);
+      // operands of chunk j: the src z-line and kappa of the lane's cell
+      auto load = [&](int j, T(&u)[n], T &kap) {
+        const int jx = j % NCX, jy = (j / NCX) % NCY, jz = j / (NCX * NCY);
+        const uint32_t sc = uint32_t(jx * CX * K) + uint32_t(N1) * uint32_t(jy * BY * K) +
+                            uint32_t(plane) * uint32_t(jz * BZ * K);
+#pragma unroll
+        for (int l = 0; l < n; ++l) u[l] = buf_load<T>(rs, so, uint32_t(sizeof(T)) * (sc + uint32_t(plane) * l));
+        const uint32_t kc = uint32_t(jx * CX) + uint32_t(Nc) * (uint32_t(jy * BY) + uint32_t(Nc) * uint32_t(jz * BZ));
+        kap = buf_load<T>(rk, ko, uint32_t(sizeof(T)) * kc);
+      };
+      CellCtx cc;
+      cc.i0 = i0;
+      cc.i1 = i1;
+      cc.inblk = inblk;
+      T u[n];
+      T kap;
+      load(0, u, kap);
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) {
+        const int jx = j % NCX, jy = (j / NCX) % NCY, jz = j / (NCX * NCY);
+        double *ctile = tile + ((jz * BZ + lz) * K) * (TX * TY) + ((jy * BY + ly) * K) * TX + (jx * CX + lx) * K;
+        T kn = kap;
+        cart_cell<K, T, TX, TY, WL>(cc, u, kap * h, A, B, A, B, eo, ctile, [&] {
+          if (j + 1 < NCH) load(j + 1, u, kn);
+        });
+        kap = kn;
+      }
+    }
+  }
+  if (!fast) {
   CellCtx cc;
   int64_t cell;
   cell_at(0, 0, 0, cc, cell);
@@ -486,19 +560,13 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
     cc = cn;
     cell = celln;
   }
+  }
   __syncthreads();
 
   // Stores.  Tile items with X < MX, Y < MY, Z < MZ are owned by this brick; items on the
   // upper faces are owned by a neighbouring brick (-> halo record) unless the brick is the
   // last one in every direction in which the item lies on its upper face (-> dst).
   // Dirichlet DoFs get the identity-row value src.
-  const bool lastx = bx == bg.nbx - 1, lasty = by == bg.nby - 1, lastz = bz == bg.nbz - 1;
-  const int64_t plane = int64_t(N1) * N1;
-  const int gx0 = cx0 * K, gy0 = cy0 * K, gz0 = cz0 * K;
-  const int64_t gbase = gx0 + int64_t(N1) * gy0 + plane * gz0;
-  // interior bricks without Dirichlet DoFs and without cut-off cells need no per-item tests
-  const bool plain = gx0 + MX < N1 - 1 && gy0 + MY < N1 - 1 && gz0 + MZ < N1 - 1 &&
-                     !((bg.dmask & 1) && (gx0 == 0 || gy0 == 0 || gz0 == 0));
   constexpr int OWN = MX * MY * MZ, ITO = (OWN + kBlock - 1) / kBlock;
   constexpr int HS = (MY + 1) * (MZ + 1) + MX * (MZ + 1) + MX * MY, ITH = (HS + kBlock - 1) / kBlock;
   T *hrec = halo + int64_t(brick) * HS;
@@ -802,6 +870,11 @@ BrickGrid brick_grid(int Nc, int N1, int dmask) {
   bg.nby = (Nc + Bk::y * Bk::ny - 1) / (Bk::y * Bk::ny);
   bg.nbz = (Nc + Bk::z * Bk::nz - 1) / (Bk::z * Bk::nz);
   bg.dmask = dmask;
+  // byte offsets of the interior walk from the brick's first DoF and first cell: src within
+  // the brick's mz + 1 planes of DoFs, kappa within its planes of cells
+  constexpr double lim = 2147483648.0;
+  const double plane = double(N1) * N1, cplane = double(Nc) * Nc;
+  bg.off32 = sizeof(T) * plane * (bg.mz + 1) < lim && sizeof(T) * cplane * (Bk::z * Bk::nz + 1) < lim;
   return bg;
 }
 

@@ -115,109 +115,166 @@ cheb_step_kernel(const T *__restrict__ b, const T *__restrict__ ax, const T *__r
   }
 }
 
-// fine += P coarse over one coarse cell per work-group: embedding of the coarse Q_k
-// basis at the (2k+1)^3 fine nodes, applied direction by direction.  Each fine node is
-// written by exactly one coarse cell (half-open ownership), so no atomics are needed.
-// A coarse cell covers only 2k fine DoFs of each fine row, so neighbouring cells in x share
-// the fine rows' cache lines: the blocks of one XCD take consecutive cells (xcd_block), so
-// that those lines are reused in that XCD's L2 instead of being fetched by several XCDs.
-template <int K, typename TC, typename TF>
+// Coarse cells per work-group of the transfer kernels (a row along x): fine rows of up to
+// about 65 values (2kR + 1), as far as a (2kR + 1)(2k + 1)^2 fine tile stays within LDS bytes.
+// Fine rows then move in long contiguous segments, and the work-group's barriers are shared
+// by R cells.  The restriction, whose load phase waits on two fine vectors, keeps a smaller
+// tile for more resident work-groups.
+#ifndef MFL_RESTRICT_LDS
+#define MFL_RESTRICT_LDS 12288
+#endif
+constexpr int kProlongLds = 32768, kRestrictLds = MFL_RESTRICT_LDS;
+template <int K, typename TF, int LDS>
+constexpr int transfer_row() {
+  constexpr int m = 2 * K + 1;
+  constexpr int by_len = 32 / K;
+  constexpr int by_lds = ((LDS / (m * m * int(sizeof(TF)))) - 1) / (2 * K);
+  constexpr int r = by_len < by_lds ? by_len : by_lds;
+  return r < 1 ? 1 : r;
+}
+
+// Work-group -> row of coarse cells (rx-th row of R cells along x of line (cy, cz)).
+struct TransferRow {
+  int cx0, nc, cy, cz;
+  template <int R>
+  __device__ static TransferRow at(int blk, int Ncc) {
+    const int nrow = (Ncc + R - 1) / R;
+    TransferRow t;
+    const int rx = blk % nrow;
+    t.cy = (blk / nrow) % Ncc;
+    t.cz = blk / (nrow * Ncc);
+    t.cx0 = rx * R;
+    t.nc = min(R, Ncc - t.cx0);
+    return t;
+  }
+};
+
+// Work-groups of a transfer with rows of R coarse cells; a level whose rows would give fewer
+// than kRowMinBlocks work-groups (coarse multigrid levels) uses one cell per work-group, so
+// that it still spreads over the chip.
+constexpr int kRowMinBlocks = 2048;
+inline int transfer_blocks(int R, int Ncc) { return ((Ncc + R - 1) / R) * Ncc * Ncc; }
+template <int R>
+inline bool use_rows(int Ncc) { return R > 1 && transfer_blocks(R, Ncc) >= kRowMinBlocks; }
+
+// fine += P coarse over a row of up to R coarse cells per work-group: embedding of the
+// coarse Q_k basis at the fine nodes, applied direction by direction (z, y on the row's
+// coarse points, then x to the fine points).  Each fine node is written by exactly one
+// coarse cell (half-open ownership), so no atomics are needed.  Work-groups of one XCD take
+// consecutive rows (xcd_block), so that the fine rows' cache lines that neighbouring rows
+// share stay in that XCD's L2.
+template <int K, typename TC, typename TF, int R>
 __global__ void __launch_bounds__(kBlock)
 prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int dmask, TransferTab tt) {
-  constexpr int n = K + 1, m = 2 * K + 1;
-  constexpr int s0 = (n * n * n > m * m * n) ? n * n * n : m * m * n;
+  constexpr int n = K + 1, m = 2 * K + 1, CX = K * R + 1, FX = 2 * K * R + 1;
   __shared__ double P[m * n];
-  __shared__ TF b0[s0], b1[m * n * n];
+  __shared__ TF b0[n * n * CX], b1[m * n * CX], b2[m * m * CX];   // [l][b][X], [L][b][X], [L][J][X]
   for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
-  const int64_t cell = xcd_block(blockIdx.x, gridDim.x);
-  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
+  const TransferRow w = TransferRow::at<R>(xcd_block(blockIdx.x, gridDim.x), Ncc);
   const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
-  for (int i = threadIdx.x; i < n * n * n; i += kBlock) {
-    const int a = i % n, b = (i / n) % n, l = i / (n * n);
-    const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
-    const bool bnd = dirichlet_dof(gx, gy, gz, N1c, dmask);
+  const int cxn = K * w.nc + 1;   // coarse points of the row along x (the tiles hold CX)
+  // (index decompositions use the compile-time extents; entries past the row stay unused)
+  for (int i = threadIdx.x; i < n * n * CX; i += kBlock) {
+    const int X = i % CX, bl = i / CX, b = bl % n, l = bl / n;
+    const int gx = K * w.cx0 + X, gy = w.cy * K + b, gz = w.cz * K + l;
+    const bool bnd = X >= cxn || dirichlet_dof(gx, gy, gz, N1c, dmask);
     b0[i] = bnd ? TF(0) : TF(xc[gx + int64_t(N1c) * (gy + int64_t(N1c) * gz)]);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m * n * n; i += kBlock) {   // z: [L][j][i]
-    const int a = i % n, b = (i / n) % n, L = i / (n * n);
+  for (int i = threadIdx.x; i < m * n * CX; i += kBlock) {   // z
+    const int X = i % CX, Lb = i / CX, b = Lb % n, L = Lb / n;
     TF s = 0;
-    for (int l = 0; l < n; ++l) s += TF(P[L * n + l]) * b0[l * n * n + b * n + a];
+#pragma unroll
+    for (int l = 0; l < n; ++l) s += TF(P[L * n + l]) * b0[(l * n + b) * CX + X];
     b1[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m * m * n; i += kBlock) {   // y: [L][J][i]
-    const int a = i % n, J = (i / n) % m, L = i / (n * m);
+  for (int i = threadIdx.x; i < m * m * CX; i += kBlock) {   // y
+    const int X = i % CX, LJ = i / CX, J = LJ % m, L = LJ / m;
     TF s = 0;
-    for (int b = 0; b < n; ++b) s += TF(P[J * n + b]) * b1[L * n * n + b * n + a];
-    b0[i] = s;
+#pragma unroll
+    for (int b = 0; b < n; ++b) s += TF(P[J * n + b]) * b1[(L * n + b) * CX + X];
+    b2[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m * m * m; i += kBlock) {   // x: fine node (I, J, L)
-    const int I = i % m, J = (i / m) % m, L = i / (m * m);
-    if ((I == m - 1 && cx < Ncc - 1) || (J == m - 1 && cy < Ncc - 1) || (L == m - 1 && cz < Ncc - 1))
-      continue;                                             // owned by the next coarse cell
-    const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
+  // x: the fine points of the row that it owns: below the next row's first point unless the
+  // row ends the line, J and L below the cell's upper face unless it is the last cell in that
+  // direction (half-open ownership)
+  const int fxn = 2 * K * w.nc + (w.cx0 + w.nc == Ncc ? 1 : 0);
+  for (int i = threadIdx.x; i < FX * m * m; i += kBlock) {
+    const int I = i % FX, JL = i / FX, J = JL % m, L = JL / m;
+    if (I >= fxn || (J == m - 1 && w.cy < Ncc - 1) || (L == m - 1 && w.cz < Ncc - 1)) continue;
+    const int c = min(I / (2 * K), R - 1), Ic = I - 2 * K * c;   // cell of the row, local index
+    const int fx = 2 * K * w.cx0 + I, fy = 2 * K * w.cy + J, fz = 2 * K * w.cz + L;
     if (dirichlet_dof(fx, fy, fz, N1f, dmask)) continue;
     TF s = 0;
-    for (int a = 0; a < n; ++a) s += TF(P[I * n + a]) * b0[L * m * n + J * n + a];
+#pragma unroll
+    for (int a = 0; a < n; ++a) s += TF(P[Ic * n + a]) * b2[JL * CX + K * c + a];
     xf[fx + int64_t(N1f) * (fy + int64_t(N1f) * fz)] += s;
   }
 }
 
 // Restriction coarse = P^T (b_f - A x_f) (axf == nullptr: P^T b_f) in two kernels without
-// atomics.  restrict_cell_kernel: one coarse cell per work-group applies the transposed
-// embedding to the (2k+1)^3 fine values of the cell, fine nodes shared by several coarse
-// cells weighted by 1/multiplicity so that the sum over cells is P^T, and stores the cell's
-// n^3 contributions contiguously in `cellbuf` (block order as in prolongate_kernel:
-// consecutive cells on one XCD share the fine rows' cache lines).  restrict_gather_kernel:
-// each coarse DoF sums the contributions of the 1 to 8 cells that contain it, in a fixed
-// order, and is written once (zero on Dirichlet DoFs).
-template <int K, typename TF>
+// atomics.  restrict_cell_kernel: a row of up to R coarse cells per work-group loads the
+// row's fine tile once (fine nodes shared by several coarse cells weighted by
+// 1/multiplicity, so that the sum over cells is P^T), applies the transposed embedding of
+// each cell (x, y, z) and stores each cell's n^3 contributions contiguously in `cellbuf`.
+// restrict_gather_kernel: each coarse DoF sums the contributions of the 1 to 8 cells that
+// contain it, in a fixed order, and is written once (zero on Dirichlet DoFs).
+template <int K, typename TF, int R>
 __global__ void __launch_bounds__(kBlock)
 restrict_cell_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TF *__restrict__ cellbuf, int Ncc,
                      int dmask, TransferTab tt) {
-  constexpr int n = K + 1, m = 2 * K + 1;
+  constexpr int n = K + 1, m = 2 * K + 1, FX = 2 * K * R + 1;
+  constexpr int RS = FX * m * m > R * m * n * n ? FX * m * m : R * m * n * n;
   __shared__ double P[m * n];
-  __shared__ TF r[m * m * m], t1[m * m * n];
+  __shared__ TF r[RS], t1[R * m * m * n];   // r: [L][J][X], then [c][L][b][a]; t1: [c][L][J][a]
   for (int i = threadIdx.x; i < m * n; i += kBlock) P[i] = tt.P[i];
-  const int64_t cell = xcd_block(blockIdx.x, gridDim.x);
-  const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
-  const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
-  for (int i = threadIdx.x; i < m * m * m; i += kBlock) {
-    const int I = i % m, J = (i / m) % m, L = i / (m * m);
-    const int fx = 2 * K * cx + I, fy = 2 * K * cy + J, fz = 2 * K * cz + L;
+  const TransferRow w = TransferRow::at<R>(xcd_block(blockIdx.x, gridDim.x), Ncc);
+  const int N1f = 2 * K * Ncc + 1;
+  const int fxn = 2 * K * w.nc + 1;   // fine points of the row along x (the tile holds FX)
+  // weight 1/2 per direction in which the fine node lies on a face shared by two coarse cells
+  auto shared_half = [&](int f) { return f % (2 * K) == 0 && f > 0 && f < N1f - 1; };
+  // (index decompositions use the compile-time extents; cells past the row are skipped)
+  for (int i = threadIdx.x; i < FX * m * m; i += kBlock) {
+    const int X = i % FX, JL = i / FX, J = JL % m, L = JL / m;
+    const int fx = 2 * K * w.cx0 + X, fy = 2 * K * w.cy + J, fz = 2 * K * w.cz + L;
     TF v = 0;
-    if (!dirichlet_dof(fx, fy, fz, N1f, dmask)) {
+    if (X < fxn && !dirichlet_dof(fx, fy, fz, N1f, dmask)) {
       const int64_t g = fx + int64_t(N1f) * (fy + int64_t(N1f) * fz);
       TF wgt = 1;
-      if ((I == 0 && cx > 0) || (I == m - 1 && cx < Ncc - 1)) wgt *= TF(0.5);
-      if ((J == 0 && cy > 0) || (J == m - 1 && cy < Ncc - 1)) wgt *= TF(0.5);
-      if ((L == 0 && cz > 0) || (L == m - 1 && cz < Ncc - 1)) wgt *= TF(0.5);
+      if (shared_half(fx)) wgt *= TF(0.5);
+      if (shared_half(fy)) wgt *= TF(0.5);
+      if (shared_half(fz)) wgt *= TF(0.5);
       v = wgt * (axf ? bf[g] - axf[g] : bf[g]);
     }
     r[i] = v;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m * m * n; i += kBlock) {   // x: [L][J][a]
-    const int a = i % n, J = (i / n) % m, L = i / (n * m);
+  for (int i = threadIdx.x; i < R * m * m * n; i += kBlock) {   // x: [c][L][J][a]
+    const int a = i % n, cLJ = i / n, LJ = cLJ % (m * m), c = cLJ / (m * m);
     TF s = 0;
-    for (int I = 0; I < m; ++I) s += TF(P[I * n + a]) * r[L * m * m + J * m + I];
+#pragma unroll
+    for (int I = 0; I < m; ++I) s += TF(P[I * n + a]) * r[LJ * FX + 2 * K * c + I];
     t1[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m * n * n; i += kBlock) {   // y: [L][b][a] (reuses r)
-    const int a = i % n, b = (i / n) % n, L = i / (n * n);
+  for (int i = threadIdx.x; i < R * m * n * n; i += kBlock) {   // y: [c][L][b][a] (reuses r)
+    const int a = i % n, b = (i / n) % n, cL = i / (n * n);   // cL = c m + L
     TF s = 0;
-    for (int J = 0; J < m; ++J) s += TF(P[J * n + b]) * t1[L * m * n + J * n + a];
+#pragma unroll
+    for (int J = 0; J < m; ++J) s += TF(P[J * n + b]) * t1[(cL * m + J) * n + a];
     r[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n * n * n; i += kBlock) {   // z: coarse DoF (a, b, l)
-    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+  for (int i = threadIdx.x; i < R * n * n * n; i += kBlock) {   // z: coarse DoF (a, b, l) of cell c
+    const int ab = i % (n * n), l = (i / (n * n)) % n, c = i / (n * n * n);
+    if (c >= w.nc) continue;
     TF s = 0;
-    for (int L = 0; L < m; ++L) s += TF(P[L * n + l]) * r[L * n * n + b * n + a];
-    cellbuf[cell * (n * n * n) + i] = s;
+#pragma unroll
+    for (int L = 0; L < m; ++L) s += TF(P[L * n + l]) * r[(c * m + L) * n * n + ab];
+    const int64_t cell = (w.cx0 + c) + int64_t(Ncc) * (w.cy + int64_t(Ncc) * w.cz);
+    cellbuf[cell * (n * n * n) + l * n * n + ab] = s;
   }
 }
 
@@ -433,16 +490,28 @@ hipError_t launch_cheb_step(const void *b, const void *ax, const void *dinv, voi
   return hipGetLastError();
 }
 
+// prolongation rows: measured faster up to k = 4 on the fine levels, slower above
+template <int K, typename TC, typename TF>
+static void prolongate_kt(const Context &c, const Level &coarse, const void *xc, void *xf, hipStream_t s) {
+  constexpr int R = K <= 4 ? transfer_row<K, TF, kProlongLds>() : 1;
+  const int Ncc = coarse.Nc, dm = dirichlet_mask(c.p);
+  if (use_rows<R>(Ncc))
+    prolongate_kernel<K, TC, TF, R><<<transfer_blocks(R, Ncc), kBlock, 0, s>>>((const TC *)xc, (TF *)xf, Ncc, dm,
+                                                                               c.transfer);
+  else
+    prolongate_kernel<K, TC, TF, 1><<<transfer_blocks(1, Ncc), kBlock, 0, s>>>((const TC *)xc, (TF *)xf, Ncc, dm,
+                                                                               c.transfer);
+}
+
 template <int K>
 static hipError_t prolongate_k(const Context &c, const Level &coarse, const void *xc, int cd,
                                void *xf, int fd, hipStream_t s) {
-  const int grid = int(coarse.ncells);
   if (cd == MFL_F64 && fd == MFL_F64)
-    prolongate_kernel<K, double, double><<<grid, kBlock, 0, s>>>((const double *)xc, (double *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
+    prolongate_kt<K, double, double>(c, coarse, xc, xf, s);
   else if (cd == MFL_F64 && fd == MFL_F32)
-    prolongate_kernel<K, double, float><<<grid, kBlock, 0, s>>>((const double *)xc, (float *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
+    prolongate_kt<K, double, float>(c, coarse, xc, xf, s);
   else if (cd == MFL_F32 && fd == MFL_F32)
-    prolongate_kernel<K, float, float><<<grid, kBlock, 0, s>>>((const float *)xc, (float *)xf, coarse.Nc, dirichlet_mask(c.p), c.transfer);
+    prolongate_kt<K, float, float>(c, coarse, xc, xf, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -461,8 +530,14 @@ template <int K, typename TF, typename TC>
 static hipError_t restrict_kt(const Context &c, const Level &coarse, const Level &fine, const void *bf,
                               const void *axf, void *bc, hipStream_t s) {
   TF *cellbuf = static_cast<TF *>(fine.tbuf);
-  restrict_cell_kernel<K, TF><<<int(coarse.ncells), kBlock, 0, s>>>((const TF *)bf, (const TF *)axf, cellbuf,
-                                                                    coarse.Nc, dirichlet_mask(c.p), c.transfer);
+  constexpr int R = transfer_row<K, TF, kRestrictLds>();
+  const int Ncc = coarse.Nc, dm = dirichlet_mask(c.p);
+  if (use_rows<R>(Ncc))
+    restrict_cell_kernel<K, TF, R><<<transfer_blocks(R, Ncc), kBlock, 0, s>>>((const TF *)bf, (const TF *)axf,
+                                                                              cellbuf, Ncc, dm, c.transfer);
+  else
+    restrict_cell_kernel<K, TF, 1><<<transfer_blocks(1, Ncc), kBlock, 0, s>>>((const TF *)bf, (const TF *)axf,
+                                                                              cellbuf, Ncc, dm, c.transfer);
   restrict_gather_kernel<K, TF, TC><<<grid_for(coarse.ndofs), kBlock, 0, s>>>(cellbuf, (TC *)bc, coarse.Nc,
                                                                               dirichlet_mask(c.p));
   return hipGetLastError();

@@ -199,6 +199,12 @@ rhs_kernel(double *__restrict__ b, int Nc, int N1, double h, double lo, double a
   const int c[3] = {int(cell % Nc), int((cell / Nc) % Nc), int(cell / (int64_t(Nc) * Nc))};
   for (int q = threadIdx.x; q < n3; q += kBlock) {
     const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+    if (amp == 0.0) {
+      // affine cell: x_q = lo + (c + xi_q) h, det J = h^3
+      const double xq[3] = {lo + (c[0] + tb.xg[q0]) * h, lo + (c[1] + tb.xg[q1]) * h, lo + (c[2] + tb.xg[q2]) * h};
+      fw[q] = w[q0] * w[q1] * w[q2] * h * h * h * F()(xq);
+      continue;
+    }
     double X[3][n], s1[3][n];
     for (int d = 0; d < 3; ++d)
       for (int i = 0; i < n; ++i) {

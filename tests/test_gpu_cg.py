@@ -82,7 +82,8 @@ def test_apply_cartesian_tall_bricks_sampled(k, Nc, nrows):
     """Meshes large enough for the taller Cartesian brick shapes (a level uses them only when
     they give at least 512 bricks): sampled rows against the oracle's element-by-element rows,
     concentrated on DoF planes at multiples of 6, 12 and 24 intervals (the brick faces, edges
-    and corners of those shapes), FP64 and FP32, mixed boundary conditions.  (Q6 uses the
+    and corners of those shapes), FP64 and FP32, mixed boundary conditions, a cellwise
+    coefficient (interior bricks read it through their own load path).  (Q6 uses the
     chunk pattern of Q5; its oracle rows take minutes.)"""
     box = Box(Nc, k)
     N1 = k * Nc + 1
@@ -93,8 +94,9 @@ def test_apply_cartesian_tall_bricks_sampled(k, Nc, nrows):
     rows = np.unique(np.concatenate([g[:, 0] + N1 * (g[:, 1] + N1 * g[:, 2]),
                                      rng.integers(0, box.n_dofs, nrows // 3)]))
     u = uniform_vector(box.n_dofs, 80 + k)
-    ref = o_cg.apply_rows(box, u, rows, bc="mixed")
-    prob = mfl.Problem(k, Nc, bc=mfl.MIXED)
+    kap = kappa_field(box.n_cells)
+    ref = o_cg.apply_rows(box, u, rows, kappa=kap, bc="mixed")
+    prob = mfl.Problem(k, Nc, kappa=kap, bc=mfl.MIXED)
     y = prob.apply(t(u)).cpu().numpy()[rows]
     assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
     y32 = prob.apply(t(u, torch.float32)).double().cpu().numpy()[rows]
@@ -106,7 +108,7 @@ def test_apply_cartesian_default_bricks_sampled(k, Nc, extents):
     """Meshes with enough default (multi-chunk) bricks that neither the tall nor the one-chunk
     shape of small multigrid levels is used (the smaller meshes above take the one-chunk
     bricks): sampled rows concentrated on the brick faces (DoF planes at multiples of the
-    brick extents), FP64 and FP32, mixed boundary conditions."""
+    brick extents), FP64 and FP32, mixed boundary conditions, a cellwise coefficient."""
     box = Box(Nc, k)
     N1 = k * Nc + 1
     rng = np.random.default_rng(90 + k)
@@ -115,8 +117,9 @@ def test_apply_cartesian_default_bricks_sampled(k, Nc, extents):
     g = rng.choice(marks, size=(200, 3))
     rows = np.unique(np.concatenate([g[:, 0] + N1 * (g[:, 1] + N1 * g[:, 2]), rng.integers(0, box.n_dofs, 100)]))
     u = uniform_vector(box.n_dofs, 95 + k)
-    ref = o_cg.apply_rows(box, u, rows, bc="mixed")
-    prob = mfl.Problem(k, Nc, bc=mfl.MIXED)
+    kap = kappa_field(box.n_cells)
+    ref = o_cg.apply_rows(box, u, rows, kappa=kap, bc="mixed")
+    prob = mfl.Problem(k, Nc, kappa=kap, bc=mfl.MIXED)
     y = prob.apply(t(u)).cpu().numpy()[rows]
     assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
     y32 = prob.apply(t(u, torch.float32)).double().cpu().numpy()[rows]

@@ -90,3 +90,43 @@ def test_transfer_matches_oracle_embedding(k):
     rc = torch.empty(coarse.n_dofs, dtype=torch.float64, device="cuda")
     prob.transfer(lev, 1, torch.tensor(uf, device="cuda"), rc)
     assert rel_err(rc, P.T @ uf) <= 1e-13
+
+
+@pytest.mark.parametrize("k,nf", [(1, 128), (2, 64), (3, 64), (4, 64), (5, 64)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_transfer_rows_full_size(k, nf, dtype):
+    """Transfers on a fine level large enough that a work-group takes a row of coarse cells
+    (the meshes above take one cell per work-group), checked by properties that hold at any
+    size, with mixed boundary conditions (Dirichlet DoFs masked on both levels):
+    - prolongation reproduces, at the fine nodes, a polynomial of degree k per direction that
+      vanishes on the Dirichlet faces (it lies in the coarse space);
+    - restriction is its transpose: <P c, f> = <c, P^T f> for seeded random c and f."""
+    print("transfer rows Q%d fine %d^3 %s" % (k, nf, dtype), flush=True)
+    prob = mfl.Problem(k, nf, bc=mfl.MIXED, build_mg=True)
+    lev = prob.num_levels - 1
+    fine, coarse = Box(nf, k), Box(nf // 2, k)
+    rng = np.random.default_rng(300 + k)
+
+    def poly_values(box, coef):
+        # prod_d (1 - x_d) r_d(x_d), r_d of degree k - 1: zero on the faces x_d = 1
+        x = box.node_coords_1d()
+        q = [torch.tensor((1 - x) * np.polyval(coef[d], x), device="cuda") for d in range(3)]
+        return (q[2][:, None, None] * q[1][None, :, None] * q[0][None, None, :]).reshape(-1)
+
+    coef = rng.uniform(-1, 1, (3, k))
+    pc, pf = poly_values(coarse, coef), poly_values(fine, coef)
+    out = torch.zeros(fine.n_dofs, dtype=dtype, device="cuda")
+    prob.transfer(lev, 0, pc.to(dtype), out)
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    assert (out.double() - pf).abs().max().item() <= tol * pf.abs().max().item()
+
+    c = torch.tensor(uniform_vector(coarse.n_dofs, 320 + k), device="cuda").to(dtype)
+    f = torch.tensor(uniform_vector(fine.n_dofs, 330 + k), device="cuda").to(dtype)
+    pcv = torch.zeros(fine.n_dofs, dtype=dtype, device="cuda")
+    prob.transfer(lev, 0, c, pcv)
+    rf = torch.empty(coarse.n_dofs, dtype=dtype, device="cuda")
+    prob.transfer(lev, 1, f, rf)
+    lhs = torch.dot(pcv.double(), f.double()).item()
+    rhs = torch.dot(c.double(), rf.double()).item()
+    scale = (pcv.double().abs() * f.double().abs()).sum().item()
+    assert abs(lhs - rhs) <= (1e-13 if dtype == torch.float64 else 1e-6) * scale
