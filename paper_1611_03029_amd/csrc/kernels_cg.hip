@@ -667,67 +667,97 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
 // positive multiple of the brick extent M in some direction).  Each such DoF is visited
 // once (x faces, then y faces off x faces, then z faces off both; x is the fastest index
 // within the y and z faces) and sums, in a fixed order, the upper-face values of the 1, 3
-// or 7 lower bricks sharing it.  32-bit index arithmetic (checked on the host).
+// or 7 lower bricks sharing it.  A thread takes kHaloPer face positions kBlock apart and
+// issues the loads of all of them before the first store; 32-bit index arithmetic with
+// multiply-shift divisions (sizes checked on the host).
+constexpr int kHaloPer = 4;
+struct HaloDiv {
+  FastDiv plane, n1, mx, my, mz;
+};
+
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
-halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg) {
+halo_add_kernel(T *__restrict__ dst, const T *__restrict__ halo, BrickGrid bg, HaloDiv hv) {
   const int MX = bg.sx * K, MY = bg.my, MZ = bg.mz;
   const unsigned N1 = bg.N1, P = N1 * N1;
   const unsigned fx = unsigned(bg.nbx - 1) * P, fy = unsigned(bg.nby - 1) * P,
                  fz = unsigned(bg.nbz - 1) * P;
   const unsigned total = fx + fy + fz;
   const int hs = halo_size(MX, MY, MZ);
-  for (unsigned id = blockIdx.x * kBlock + threadIdx.x; id < total; id += gridDim.x * kBlock) {
-    int g[3];
-    if (id < fx) {
-      const unsigned f = id / P, r = id - f * P;
-      g[0] = int(f + 1) * MX;
-      g[2] = int(r / N1);
-      g[1] = int(r - unsigned(g[2]) * N1);
-    } else if (id < fx + fy) {
-      const unsigned q = id - fx, f = q / P, r = q - f * P;
-      g[1] = int(f + 1) * MY;
-      g[2] = int(r / N1);
-      g[0] = int(r - unsigned(g[2]) * N1);
-      if (g[0] % MX == 0 && g[0] / MX >= 1 && g[0] / MX < bg.nbx) continue;   // on an x face
-    } else {
-      const unsigned q = id - fx - fy, f = q / P, r = q - f * P;
-      g[2] = int(f + 1) * MZ;
-      g[1] = int(r / N1);
-      g[0] = int(r - unsigned(g[1]) * N1);
-      if (g[0] % MX == 0 && g[0] / MX >= 1 && g[0] / MX < bg.nbx) continue;
-      if (g[1] % MY == 0 && g[1] / MY >= 1 && g[1] / MY < bg.nby) continue;
-    }
-    if (dirichlet_dof(g[0], g[1], g[2], N1, bg.dmask))
-      continue;
-    const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
-    int b[3], X[3];
-    bool sh[3];
-    for (int d = 0; d < 3; ++d) {
-      b[d] = min(g[d] / M[d], NB[d] - 1);
-      X[d] = g[d] - b[d] * M[d];
-      sh[d] = X[d] == 0 && b[d] > 0;
+  const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
+  const unsigned stride = gridDim.x * kBlock * kHaloPer;
+  for (unsigned base = blockIdx.x * kBlock * kHaloPer + threadIdx.x; base < total; base += stride) {
+    bool ok[kHaloPer];
+    uint32_t gi[kHaloPer];
+    int b[kHaloPer][3], X[kHaloPer][3];
+    uint8_t sh[kHaloPer];
+    T d[kHaloPer], s[kHaloPer];
+#pragma unroll
+    for (int j = 0; j < kHaloPer; ++j) {
+      const unsigned id = base + j * kBlock;
+      int g[3] = {0, 0, 0};
+      bool skip = id >= total;
+      if (!skip) {
+        // face f of the direction, position r within the face plane
+        const unsigned q = id < fx ? id : (id < fx + fy ? id - fx : id - fx - fy);
+        const unsigned f = hv.plane.div(q), r = q - f * P, hi = hv.n1.div(r), lo = r - hi * N1;
+        if (id < fx) {
+          g[0] = int(f + 1) * MX;
+          g[1] = int(lo);
+          g[2] = int(hi);
+        } else if (id < fx + fy) {
+          g[0] = int(lo);
+          g[1] = int(f + 1) * MY;
+          g[2] = int(hi);
+        } else {
+          g[0] = int(lo);
+          g[1] = int(hi);
+          g[2] = int(f + 1) * MZ;
+        }
+        const unsigned qx = hv.mx.div(unsigned(g[0])), qy = hv.my.div(unsigned(g[1]));
+        const bool onx = g[0] == int(qx) * MX && qx >= 1 && int(qx) < bg.nbx;
+        const bool ony = g[1] == int(qy) * MY && qy >= 1 && int(qy) < bg.nby;
+        skip = (id >= fx && onx) || (id >= fx + fy && ony) || dirichlet_dof(g[0], g[1], g[2], N1, bg.dmask);
+      }
+      ok[j] = !skip;
+      const int qg[3] = {int(hv.mx.div(unsigned(g[0]))), int(hv.my.div(unsigned(g[1]))), int(hv.mz.div(unsigned(g[2])))};
+      uint8_t m = 0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        b[j][e] = min(qg[e], NB[e] - 1);
+        X[j][e] = g[e] - b[j][e] * M[e];
+        if (X[j][e] == 0 && b[j][e] > 0) m |= uint8_t(1 << e);
+      }
+      sh[j] = m;
+      gi[j] = unsigned(g[0]) + N1 * (unsigned(g[1]) + N1 * unsigned(g[2]));
     }
     // record entry of the lower brick across the shared directions in mask m
-    auto entry = [&](int m) {
-      const int ob0 = b[0] - (m & 1), ob1 = b[1] - ((m >> 1) & 1), ob2 = b[2] - ((m >> 2) & 1);
-      const int tx = (m & 1) ? MX : X[0], ty = (m & 2) ? MY : X[1], tz = (m & 4) ? MZ : X[2];
+    auto entry = [&](int j, int m) {
+      const int ob0 = b[j][0] - (m & 1), ob1 = b[j][1] - ((m >> 1) & 1), ob2 = b[j][2] - ((m >> 2) & 1);
+      const int tx = (m & 1) ? MX : X[j][0], ty = (m & 2) ? MY : X[j][1], tz = (m & 4) ? MZ : X[j][2];
       const int64_t ob = ob0 + int64_t(bg.nbx) * (ob1 + int64_t(bg.nby) * ob2);
       return ob * hs + halo_index(tx, ty, tz, MX, MY, MZ);
     };
-    // dst and the first record entry (every visited DoF lies on at least one face) are loaded
-    // together; edges and corners (3 and 7 entries) add the others in increasing m
-    const int64_t gi = g[0] + int64_t(N1) * (g[1] + int64_t(N1) * g[2]);
-    const int m0 = sh[0] ? 1 : (sh[1] ? 2 : 4);
-    const T d = dst[gi];
-    T s = halo[entry(m0)];
-    if (int(sh[0]) + int(sh[1]) + int(sh[2]) > 1) {
-      for (int m = m0 + 1; m < 8; ++m) {
-        if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
-        s += halo[entry(m)];
+    // dst and the first record entry (every visited DoF lies on at least one face)
+#pragma unroll
+    for (int j = 0; j < kHaloPer; ++j) {
+      if (ok[j]) {
+        d[j] = dst[gi[j]];
+        s[j] = halo[entry(j, (sh[j] & 1) ? 1 : ((sh[j] & 2) ? 2 : 4))];
       }
     }
-    dst[gi] = d + s;
+    // edges and corners (3 and 7 entries) add the others in increasing m
+#pragma unroll
+    for (int j = 0; j < kHaloPer; ++j) {
+      if (ok[j] && (sh[j] & (sh[j] - 1))) {
+        const int m0 = (sh[j] & 1) ? 1 : ((sh[j] & 2) ? 2 : 4);
+        for (int m = m0 + 1; m < 8; ++m)
+          if ((m & sh[j]) == m) s[j] += halo[entry(j, m)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kHaloPer; ++j)
+      if (ok[j]) dst[gi[j]] = d[j] + s[j];
   }
 }
 
@@ -992,8 +1022,11 @@ static hipError_t cg_halo_k(const Context &c, const Level &L, T *dst, const T *h
                                                        : level_grid<K, T, false>(L.Nc, L.N1, dm);
   const int64_t total = int64_t(bg.nbx - 1 + bg.nby - 1 + bg.nbz - 1) * L.N1 * L.N1;
   if (total == 0) return hipSuccess;
-  if (total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit face index space
-  halo_add_kernel<K, T><<<grid_for(total, 16384), kBlock, 0, s>>>(dst, halo, bg);
+  // 32-bit face positions and DoF indices
+  if (total >= (int64_t(1) << 31) || int64_t(L.N1) * L.N1 * L.N1 >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  const HaloDiv hv{FastDiv(uint32_t(L.N1) * uint32_t(L.N1)), FastDiv(uint32_t(L.N1)), FastDiv(uint32_t(bg.sx * K)),
+                   FastDiv(uint32_t(bg.my)), FastDiv(uint32_t(bg.mz))};
+  halo_add_kernel<K, T><<<grid_for((total + kHaloPer - 1) / kHaloPer, 16384), kBlock, 0, s>>>(dst, halo, bg, hv);
   return hipGetLastError();
 }
 
