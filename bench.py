@@ -127,7 +127,10 @@ def repetitions(prob, src, dst, reps=20, per_rep=10):
     return {"reps": reps, "applies_per_rep": per_rep, "min_ms": times[0], "median_ms": times[reps // 2]}
 
 
-def hbm_ceilings(nbytes=1 << 30, reps=10):
+HBM_CEILING_BYTES = 1 << 30
+
+
+def hbm_ceilings(nbytes=HBM_CEILING_BYTES, reps=10):
     """Practical HBM rates on this GPU with library kernels: a streaming read (sum of a
     float64 tensor of nbytes) and a device copy of nbytes; best of `reps`, GB/s."""
     import torch
@@ -449,7 +452,9 @@ def reduce_traffic(fetch, write, calib_bytes, kernels, algorithmic, workload, co
     substring -> {"algorithmic_bytes": ...}, optionally "grid": the launch's grid size), from a
     FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch).  Each counter is scaled by what it
     reads for the largest plain device copy in the same run (__amd_rocclr_copyBuffer of
-    `calib_bytes` bytes each way)."""
+    `calib_bytes` bytes each way, the size of the largest copy that run makes).  WRITE_SIZE
+    counts a copy's written bytes exactly (scale 1.0 on copies of 136 MB, 453 MB and 1 GiB), so
+    a write scale away from 1 means that `calib_bytes` is not the size of that copy: refused."""
     import statistics
     f = counter_dispatches(fetch, "FETCH_SIZE")
     w = counter_dispatches(write, "WRITE_SIZE")
@@ -462,6 +467,9 @@ def reduce_traffic(fetch, write, calib_bytes, kernels, algorithmic, workload, co
 
     fk, wk = calib(f), calib(w)
     fs, ws = calib_bytes / (fk * 1024.0), calib_bytes / (wk * 1024.0)
+    if not 0.95 <= ws <= 1.05:
+        raise SystemExit("calibration copy of %d bytes does not match the largest copy of the run "
+                         "(WRITE_SIZE %.0f KiB)" % (calib_bytes, wk))
     res = {"workload": workload, "kernel_source_hash": kernel_source_hash(), "commands": commands,
            "calibration": {"kernel": "__amd_rocclr_copyBuffer (largest device copy of the run)",
                            "bytes_each_way": calib_bytes, "FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk,
@@ -627,7 +635,8 @@ def run_reduction(name, dirs):
     if name == "cg_apply_traffic":
         n, cells, q = 257 ** 3, 64 ** 3, 125
         alg = apply_bytes(n, cells, q, 8)
-        reduce_traffic(dirs[0], dirs[1], 8 * n,
+        # the run's largest device copy: the copy of the measured HBM ceilings
+        reduce_traffic(dirs[0], dirs[1], HBM_CEILING_BYTES,
                        {"apply_brick_kernel<4,double,curved>": {"match": "apply_brick_kernel<4, double, true",
                                                                 "algorithmic_bytes": alg},
                         "halo_add_kernel<4,double>": {"match": "halo_add_kernel<4, double>"}},
@@ -644,14 +653,10 @@ def run_reduction(name, dirs):
                   ("apply_brick_kernel<4, float, false", "Cartesian operator, FP32, 64^3 level", fine),
                   ("cheb_halo_kernel<4, double>", "Chebyshev update + halo, FP64, 64^3 level", 2097152),
                   ("cheb_halo_kernel<4, float>", "Chebyshev update + halo, FP32, 64^3 level", 2097152),
-                  ("restrict_xy_kernel<4, double>", "restriction x-y pass, FP64"),
-                  ("restrict_xy_kernel<4, float>", "restriction x-y pass, FP32"),
-                  ("restrict_z_kernel<4, double", "restriction z pass, FP64"),
-                  ("prolong_xy_kernel<4, double>", "prolongation x-y pass, FP64"),
-                  ("prolong_xy_kernel<4, float>", "prolongation x-y pass, FP32"),
-                  ("prolong_z_kernel<4, double", "prolongation z pass, FP64")]
-        for d in dirs[1:]:
-            pass
+                  ("restrict_cell_kernel<4, double, 2>", "restriction, rows of 2 cells, FP64, 64^3 level"),
+                  ("restrict_cell_kernel<4, float, 4>", "restriction, rows of 4 cells, FP32, 64^3 level"),
+                  ("prolongate_kernel<4, double, double, 6>", "prolongation, rows of 6 cells, FP64, 64^3 level"),
+                  ("prolongate_kernel<4, float, float, 8>", "prolongation, rows of 8 cells, FP32, 64^3 level")]
         summarize_sq(dirs[0], groups, "GMG-PCG solve kernels, CG Q4 on 64^3 Cartesian cells "
                      "(FP64 and FP32 V-cycles)", cmd, out)
         if len(dirs) > 1:
