@@ -3,14 +3,19 @@
 Timed step (the JSON `value`): one FP64 operator application dst = A src of the
 continuous Q4 Laplacian on 64^3 curved cells (257^3 = 16,974,593 DoFs; deformation
 x + 0.1 sin(pi x) sin(pi y) sin(pi z) per coordinate; 5 Gauss points per direction;
-seeded U[-1,1] input already in HBM).  value = DoFs per second of that step.
+seeded U[-1,1] input already in HBM), with the library's default for this mesh, the metric
+formed on the fly from the node displacements.  value = DoFs per second of that step.
 
 Also reported, outside the timed region:
   roofline      the dominant kernel (curved-cell operator kernel) timed with HIP events on
                 its stream (recorded by each launch's dispatch, in a second pass of the same
-                number of applications right after the timed steps), against the HBM roofline
-                with the algorithmic bytes of one application; `traffic` from the committed
-                rocprofv3 counter summary when it was taken on the current kernel source;
+                number of applications right after the timed steps), against the FP64
+                vector peak with the algorithmic flops of one application (plain
+                sum-factorization count; the model intensity is above the FP64 ridge), its
+                HBM fraction beside; `traffic` from the committed rocprofv3 counter summary
+                when it was taken on the current kernel source;
+  stored_metric_apply  the same operator with the metric stored per quadrature point (the
+                kernel read-bound by that metric stream), against the HBM roofline;
   timing_protocol  min and median ms per application over 20 repetitions of 10 back-to-back
                 applications (events on the library's stream);
   fp32_apply    the same operator in FP32 (FP32 vectors and geometry factors);
@@ -25,7 +30,7 @@ Also reported, outside the timed region:
   adjoint       forward solve + adjoint solve + gradient kernel, CG Q3 on 32^3 cells,
                 FP32 V-cycle;
   kappa_field_apply  the same apply with the variable coefficient of Sec. 4.3 folded into the
-                metric (same kernel);
+                stored metric (the stored-metric kernel);
   cpu_baseline  the CPU oracle on the host: its assembled CSR matrix of the timed operator
                 (16^3 curved cells) applied over all host threads, and its GMG-PCG solve of
                 CG Q2 on 32^3 cells.
@@ -68,25 +73,44 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
-    None when the summary is missing or was taken on another version of the kernel."""
+def measured_traffic(kernel=None):
+    """HBM bytes per launch of the dominant kernel (or of `kernel`, a label of the summary)
+    from the committed counter summary, or None when the summary is missing or was taken on
+    another version of the kernels."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
+    if kernel is not None:
+        return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
     return rec.get("hbm_bytes_per_launch")
 
 
-def apply_bytes(n_dofs, n_cells, q_per_cell, real_bytes, curved=True):
+def apply_bytes(n_dofs, n_cells, q_per_cell, real_bytes, geometry="stored"):
     """Algorithmic bytes of one CG application: read src, write dst once, one kappa per
-    cell, and on curved cells the 6-entry metric per quadrature point."""
+    cell; on curved cells either the stored 6-entry metric per quadrature point
+    (geometry "stored") or the node displacement field, one value per DoF ("otf")."""
     b = 2 * real_bytes * n_dofs + real_bytes * n_cells
-    if curved:
+    if geometry == "stored":
         b += 6 * real_bytes * q_per_cell * n_cells
+    elif geometry == "otf":
+        b += real_bytes * n_dofs
     return b
+
+
+def apply_flops(n, n_cells, geometry="stored"):
+    """Algorithmic flops of one curved CG application in the plain sum-factorization count
+    (each one-dimensional application n^2 multiply-adds per line, no even-odd saving):
+    values and gradients at the Gauss points and the test with gradients, 12 applications
+    of n^4 multiply-adds per cell, plus 9 multiply-adds per point for q = G grad u.  With the
+    metric on the fly add the gradient of the displacement field (6 applications) and the
+    closed-form metric, 31 flops per point."""
+    f = 24 * n ** 4 + 18 * n ** 3
+    if geometry == "otf":
+        f += 12 * n ** 4 + 31 * n ** 3
+    return f * n_cells
 
 
 def time_applies(prob, src, dst, steps, warmup):
@@ -634,17 +658,21 @@ def run_reduction(name, dirs):
     out = os.path.join(ROOT, spec["out"])
     if name == "cg_apply_traffic":
         n, cells, q = 257 ** 3, 64 ** 3, 125
-        alg = apply_bytes(n, cells, q, 8)
+        alg = apply_bytes(n, cells, q, 8, "otf")
         # the run's largest device copy: the copy of the measured HBM ceilings
         reduce_traffic(dirs[0], dirs[1], HBM_CEILING_BYTES,
-                       {"apply_brick_kernel<4,double,curved>": {"match": "apply_brick_kernel<4, double, true",
-                                                                "algorithmic_bytes": alg},
+                       {"apply_brick_kernel<4,double,curved,on-the-fly>": {
+                            "match": "apply_brick_kernel<4, double, true, 0, true>", "algorithmic_bytes": alg},
+                        "apply_brick_kernel<4,double,curved,stored>": {
+                            "match": "apply_brick_kernel<4, double, true, 0, false>",
+                            "algorithmic_bytes": apply_bytes(n, cells, q, 8, "stored")},
                         "halo_add_kernel<4,double>": {"match": "halo_add_kernel<4, double>"}},
-                       alg, "CG Q4 operator apply, 64^3 curved cells (257^3 DoFs), FP64",
-                       spec["runs"], out)
+                       alg, "CG Q4 operator apply, 64^3 curved cells (257^3 DoFs), FP64 (metric on the fly; "
+                       "the stored-metric apply of the same run beside it)", spec["runs"], out)
     elif name == "cg_apply_sq":
-        summarize_sq(dirs[0], [("apply_brick_kernel<4, double, true", "FP64"),
-                               ("apply_brick_kernel<4, float, true", "FP32"),
+        summarize_sq(dirs[0], [("apply_brick_kernel<4, double, true, 0, true>", "FP64, metric on the fly"),
+                               ("apply_brick_kernel<4, float, true, 0, true>", "FP32, metric on the fly"),
+                               ("apply_brick_kernel<4, double, true, 0, false>", "FP64, stored metric"),
                                ("halo_add_kernel<4, double>", "halo addition, FP64")],
                      "CG Q4 operator kernel, 64^3 curved cells (257^3 DoFs)", cmd, out)
     elif name == "cg_solve_sq":
@@ -749,6 +777,7 @@ def main():
             torch.cuda.empty_cache()
         return
     k, Nc = 4, 64
+    # the library's default for this mesh: the metric formed on the fly in every apply
     prob = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1)
     n, cells, q = prob.n_dofs, prob.n_cells, (k + 1) ** 3
     u64 = torch.tensor(uniform_vector(n, SEED_CG_Q4_CURVED), dtype=torch.float64, device="cuda")
@@ -758,23 +787,42 @@ def main():
     ms_step, kern_ms, launches = time_applies(prob, u64, y64, args.steps, args.warmup)
     progress("timed FP64 applies done")
     traffic = measured_traffic()
-    bytes64 = apply_bytes(n, cells, q, 8)
-    achieved = bytes64 / (kern_ms * 1e-3) / 1e9
+    bytes64 = apply_bytes(n, cells, q, 8, "otf")
+    flops = apply_flops(k + 1, cells, "otf")
+    achieved_tf = flops / (kern_ms * 1e-3) / 1e12
 
     u32 = u64.float()
     y32 = torch.empty_like(u32)
     ms32, kern32, _ = time_applies(prob, u32, y32, max(args.steps // 2, 10), args.warmup)
-    bytes32 = apply_bytes(n, cells, q, 4)
     del prob, u32, y32
     torch.cuda.empty_cache()
-    # the variable-coefficient curved case: the coefficient of Sec. 4.3 folded into the metric,
-    # so the same kernel and bytes as the timed step
+    # the same operator with the metric stored per quadrature point (read by every apply)
+    probs = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1, metric_mode=mfl.METRIC_STORED)
+    mss, kerns, _ = time_applies(probs, u64, y64, max(args.steps // 2, 10), args.warmup)
+    stored_bytes = apply_bytes(n, cells, q, 8, "stored")
+    stored = {"ms_per_step": mss, "dofs_per_s": n / (mss * 1e-3), "kernel_ms": kerns,
+              "algorithmic_bytes": stored_bytes,
+              "achieved_GBs": stored_bytes / (kerns * 1e-3) / 1e9,
+              "frac": stored_bytes / (kerns * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "step_frac": stored_bytes / (mss * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "traffic": measured_traffic("apply_brick_kernel<4,double,curved,stored>")}
+    u32 = u64.float()
+    y32 = torch.empty_like(u32)
+    ms32s, kern32s, _ = time_applies(probs, u32, y32, max(args.steps // 2, 10), args.warmup)
+    bytes32s = apply_bytes(n, cells, q, 4, "stored")
+    stored["fp32"] = {"ms_per_step": ms32s, "kernel_ms": kern32s,
+                      "frac": bytes32s / (kern32s * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del probs, u32, y32
+    torch.cuda.empty_cache()
+    progress("stored-metric applies done")
+    # the variable-coefficient curved case: the coefficient of Sec. 4.3 folded into the stored
+    # metric, so the kernel and bytes of the stored-metric apply
     probk = mfl.Problem(k, Nc, geometry=mfl.CURVED, curve_amp=0.1, kappa_field=mfl.KAPPA_COSINE,
                         kappa_field_amp=1e6)
     msk, kernk, _ = time_applies(probk, u64, y64, max(args.steps // 2, 10), args.warmup)
     kfield = {"ms_per_step": msk, "dofs_per_s": n / (msk * 1e-3), "kernel_ms": kernk,
-              "achieved_GBs": bytes64 / (kernk * 1e-3) / 1e9,
-              "frac": bytes64 / (kernk * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "achieved_GBs": stored_bytes / (kernk * 1e-3) / 1e9,
+              "frac": stored_bytes / (kernk * 1e-3) / 1e9 / HBM_PEAK_GBS,
               "coefficient": "1 + 1e6 prod_e cos^2(2 pi x_e + 0.1 e) at every Gauss point, folded into the metric"}
     del probk, y64
     progress("variable-coefficient applies done")
@@ -799,20 +847,22 @@ def main():
         "config": {"workload": "CG Q4 operator apply, 64^3 curved cells (257^3 DoFs), FP64",
                    "degree": k, "cells_per_dim": Nc, "n_dofs": n, "geometry": "x+0.1 sin sin sin",
                    "quadrature": "Gauss %d^3" % (k + 1), "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "measured_GBs": None if traffic is None else traffic / (kern_ms * 1e-3) / 1e9,
-                     "kernel": "apply_brick_kernel<4,double,curved>", "kernel_ms": kern_ms,
-                     "algorithmic_bytes": bytes64, "timed_launches": launches,
-                     "kernel_source_hash": kernel_source_hash(),
-                     "step_frac": bytes64 / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "step_frac_protocol_min": bytes64 / (protocol["min_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        # the metric on the fly: model intensity flops / bytes above the FP64 ridge (9.8), so
+        # the vector FP64 peak bounds it; its HBM fraction is given beside
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "apply_brick_kernel<4,double,curved,on-the-fly metric>", "kernel_ms": kern_ms,
+                     "algorithmic_flops": flops, "algorithmic_bytes": bytes64,
+                     "intensity_flop_per_byte": flops / bytes64,
+                     "hbm_frac": bytes64 / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "timed_launches": launches, "kernel_source_hash": kernel_source_hash(),
+                     "step_frac": flops / (ms_step * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                     "step_frac_protocol_min": flops / (protocol["min_ms"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
                      "hbm_ceilings_measured": ceilings},
         "equiv_dofs_per_s": cells * k ** 3 / (ms_step * 1e-3),
-        "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32,
-                       "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
-                       "frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "fp32_apply": {"ms_per_step": ms32, "dofs_per_s": n / (ms32 * 1e-3), "kernel_ms": kern32},
         "timing_protocol": protocol,
+        "stored_metric_apply": stored,
         "kappa_field_apply": kfield,
         "calibration_copy": calib,
         "paper_context": {"cg_curved_q4_dofs_per_s": 4.58e8,

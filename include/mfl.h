@@ -72,6 +72,11 @@ extern "C" {
 #define MFL_KAPPA_CELLWISE 0   /* kappa constant in each cell (the kappa_cells array, or 1) */
 #define MFL_KAPPA_COSINE 1     /* ... times the position-dependent field of Sec. 4.3 (below) */
 
+/* metric_mode */
+#define MFL_METRIC_AUTO 0
+#define MFL_METRIC_STORED 1
+#define MFL_METRIC_ON_THE_FLY 2
+
 typedef struct mfl_params {
   int degree;             /* polynomial degree k, 1..8 */
   int cells_per_dim;      /* N_c of the finest level, >= 1 */
@@ -108,6 +113,18 @@ typedef struct mfl_params {
                              with a per-point metric) and the continuous discretization.
                              Every multigrid level evaluates it at its own quadrature points. */
   double kappa_field_amp; /* amplitude of that field (default 1e6, the paper's; >= 0) */
+  int metric_mode;        /* curved CG meshes (Sec. 3: the geometry of non-affine cells):
+                             MFL_METRIC_AUTO (default): on the fly with a cellwise kappa,
+                             stored with the position-dependent kappa field;
+                             MFL_METRIC_STORED: G_q = w_q det J_q J_q^{-1} J_q^{-T} per
+                             quadrature point, computed at setup and read by every apply
+                             (48 B per point in FP64 plus an FP32 copy);
+                             MFL_METRIC_ON_THE_FLY: only the node displacement d of the
+                             map x = X + d(X) (1,1,1) is stored (one value per DoF); every
+                             apply forms grad d at the quadrature points by sum
+                             factorization and G_q from J = h I + (1,1,1) (grad d)^T in
+                             closed form.  Needs kappa_field = MFL_KAPPA_CELLWISE.
+                             Ignored on Cartesian meshes. */
 } mfl_params;
 
 typedef struct mfl_context *mfl_handle;
@@ -122,12 +139,14 @@ int mfl_default_params(mfl_params *p);
  * reducible by halving to min_level_cells when build_mg = 1, SIPG with curved
  * geometry, multigrid with Neumann conditions on every face, a curved mesh off the unit
  * cube, a coarsest multigrid level with more than 20000 unknowns, the position-dependent
- * kappa field without curved CG geometry). */
+ * kappa field without curved CG geometry, an unknown metric_mode or the on-the-fly metric
+ * with the position-dependent kappa field). */
 int mfl_query(const mfl_params *p, int64_t *n_dofs, int64_t *n_cells, int64_t *workspace_bytes);
 
 /* Build the level hierarchy in `workspace` (device memory, >= the queried size, 256-byte
- * aligned): geometry factors (Sec. 3: per-quadrature-point metric on curved meshes, one
- * scalar per cell on Cartesian ones), Jacobi diagonals, and for build_mg = 1 the
+ * aligned): geometry factors (Sec. 3: per-quadrature-point metric or node displacement
+ * field on curved meshes, see metric_mode; one scalar per cell on Cartesian ones), Jacobi
+ * diagonals, and for build_mg = 1 the
  * lambda_max estimates of every level (Sec. 4.1) and the coarse solver's eigenvalue range
  * (the extreme eigenvalues of the Jacobi-preconditioned coarsest operator, by Lanczos with
  * full reorthogonalization until both have converged to rounding).

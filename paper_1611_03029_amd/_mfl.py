@@ -17,6 +17,7 @@ CARTESIAN, CURVED = 0, 1
 DIRICHLET, NEUMANN, MIXED = 0, 1, 2
 DG_JACOBI_GAUSS, DG_JACOBI_GLL = 0, 1
 KAPPA_CELLWISE, KAPPA_COSINE = 0, 1
+METRIC_AUTO, METRIC_STORED, METRIC_ON_THE_FLY = 0, 1, 2
 F64, F32 = 0, 1
 _DT = {F64: torch.float64, F32: torch.float32}
 
@@ -50,6 +51,7 @@ class Params(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("kappa_field", ctypes.c_int),
         ("kappa_field_amp", ctypes.c_double),
+        ("metric_mode", ctypes.c_int),
     ]
 
 
@@ -115,7 +117,7 @@ def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.
                 penalty_factor=1.0, build_mg=False, mg_precision=F64, min_level_cells=2,
                 cheb_degree=5, cheb_lo=0.06, cheb_hi=1.2, eig_iters=15, coarse_tol=1e-3,
                 domain_lo=0.0, domain_len=1.0, dg_jacobi_basis=DG_JACOBI_GLL, use_graphs=True,
-                kappa_field=KAPPA_CELLWISE, kappa_field_amp=1e6):
+                kappa_field=KAPPA_CELLWISE, kappa_field_amp=1e6, metric_mode=METRIC_AUTO):
     p = Params()
     _check(lib().mfl_default_params(ctypes.byref(p)))
     p.degree, p.cells_per_dim, p.min_level_cells = degree, cells_per_dim, min_level_cells
@@ -127,6 +129,7 @@ def make_params(degree, cells_per_dim, disc=CG, geometry=CARTESIAN, curve_amp=0.
     p.dg_jacobi_basis = dg_jacobi_basis
     p.use_graphs = int(bool(use_graphs))
     p.kappa_field, p.kappa_field_amp = kappa_field, kappa_field_amp
+    p.metric_mode = metric_mode
     return p
 
 

@@ -87,6 +87,11 @@ int check_params(const mfl_params *p) {
   }
   if (p->kappa_field != MFL_KAPPA_CELLWISE && p->kappa_field != MFL_KAPPA_COSINE)
     return fail(MFL_EINVAL, "unknown kappa_field %d", p->kappa_field);
+  if (p->metric_mode != MFL_METRIC_AUTO && p->metric_mode != MFL_METRIC_STORED &&
+      p->metric_mode != MFL_METRIC_ON_THE_FLY)
+    return fail(MFL_EINVAL, "unknown metric_mode %d", p->metric_mode);
+  if (p->metric_mode == MFL_METRIC_ON_THE_FLY && p->kappa_field != MFL_KAPPA_CELLWISE)
+    return fail(MFL_EINVAL, "the on-the-fly metric needs a cellwise kappa (kappa_field = MFL_KAPPA_CELLWISE)");
   if (p->kappa_field == MFL_KAPPA_COSINE) {
     if (p->disc != MFL_DISC_CG || p->geometry != MFL_GEOM_CURVED)
       return fail(MFL_EINVAL, "the position-dependent kappa field needs the continuous discretization on "
@@ -148,8 +153,13 @@ int64_t layout(Context &c, char *base) {
     L.kappa64 = b.take<double>(L.ncells);
     L.kappa32 = b.take<float>(L.ncells);
     if (cg && p.geometry == MFL_GEOM_CURVED) {
-      L.metric64 = b.take<double>(L.ncells * 6 * n3);
-      L.metric32 = b.take<float>(L.ncells * 6 * n3);
+      if (metric_on_the_fly(p)) {
+        L.disp64 = b.take<double>(L.ndofs);
+        L.disp32 = b.take<float>(L.ndofs);
+      } else {
+        L.metric64 = b.take<double>(L.ncells * 6 * n3);
+        L.metric32 = b.take<float>(L.ncells * 6 * n3);
+      }
     }
     if (cg) L.halo = b.take<double>(cg_halo_elements(c.k, L.Nc, p.geometry == MFL_GEOM_CURVED));
     {
@@ -738,6 +748,7 @@ int mfl_default_params(mfl_params *p) {
   p->use_graphs = 1;
   p->kappa_field = MFL_KAPPA_CELLWISE;
   p->kappa_field_amp = 1e6;
+  p->metric_mode = MFL_METRIC_AUTO;
   return MFL_OK;
 }
 

@@ -370,6 +370,98 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T (&u)[K + 
 }
 
 // ---------------------------------------------------------------------------------------
+// Curved cells with the metric formed on the fly.  The isoparametric map of the curved
+// meshes is x = X + d(X) (1,1,1) with X affine (cell size h) and d the Q_k interpolant of
+// the node displacements, so J = h I + (1,1,1) (grad d)^T: a rank-one update of h I.  With
+// g = grad d at a quadrature point and s = g_x + g_y + g_z, det J = h^2 (h + s) and
+// (Sherman-Morrison) w det J J^{-1} J^{-T} = w [(h + s) I - (1 g^T + g 1^T) + |g|^2 / (h + s) 1 1^T],
+// i.e. G_ab = w (h + s) delta_ab - w (g_a + g_b) + w |g|^2 / (h + s).
+// otf_metric forms grad d at the Gauss points of the cell by the collocation scheme of
+// curved_cell (S along z, y, x, then D along x, y, z: 6 one-dimensional applications per
+// lane in 5 phases) from the lane's z-line d of node displacements, and returns the metric
+// of the lane's z-line of Gauss points in the layout of load_metric (00, 11, 22, 01, 02, 12).
+// Buffers A..C are free again when it returns.
+template <int K, typename T, bool WL>
+__device__ __forceinline__ void otf_metric(const CellCtx &cc, const T (&d)[K + 1], T *A, T *B, T *C,
+                                           const EOTab<K + 1, T> &eo, T h, T (&g)[6][K + 1]) {
+  constexpr int n = K + 1, n2 = n * n;
+  constexpr const ct::DGTab<n, T> &gauss = ct::DGTables<n, T>::tab;   // Gauss weights w
+  const int i0 = cc.i0, i1 = cc.i1, p = i0 + n * i1;
+  if (cc.inblk) {   // z-lines: S along z
+    T t[n];
+    eo_apply<n, 1>(eo.S, d, t);
+#pragma unroll
+    for (int q = 0; q < n; ++q) A[q * n2 + p] = t[q];
+  }
+  cell_sync<WL>();
+  if (cc.inblk) {   // y-lines: S along y
+    T r[n], t[n];
+#pragma unroll
+    for (int b = 0; b < n; ++b) r[b] = A[i1 * n2 + b * n + i0];
+    eo_apply<n, 1>(eo.S, r, t);
+#pragma unroll
+    for (int q = 0; q < n; ++q) B[i1 * n2 + q * n + i0] = t[q];
+  }
+  cell_sync<WL>();
+  if (cc.inblk) {   // x-lines: S along x -> d at the Gauss points; D along x -> dd/dx
+    T r[n], v[n], dd[n];
+#pragma unroll
+    for (int a = 0; a < n; ++a) r[a] = B[i1 * n2 + i0 * n + a];
+    eo_apply<n, 1>(eo.S, r, v);
+    eo_apply<n, -1>(eo.D, v, dd);
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      A[i1 * n2 + i0 * n + q] = v[q];
+      C[i1 * n2 + i0 * n + q] = dd[q];
+    }
+  }
+  cell_sync<WL>();
+  if (cc.inblk) {   // y-lines: D along y -> dd/dy
+    T r[n], dd[n];
+#pragma unroll
+    for (int b = 0; b < n; ++b) r[b] = A[i1 * n2 + b * n + i0];
+    eo_apply<n, -1>(eo.D, r, dd);
+#pragma unroll
+    for (int q = 0; q < n; ++q) B[i1 * n2 + q * n + i0] = dd[q];
+  }
+  cell_sync<WL>();
+  if (cc.inblk) {   // z-lines: D along z -> dd/dz, then the metric of the lane's points
+    T r[n], gz[n];
+#pragma unroll
+    for (int l = 0; l < n; ++l) r[l] = A[l * n2 + p];
+    eo_apply<n, -1>(eo.D, r, gz);
+    const T w01 = gauss.w[i0] * gauss.w[i1];
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      const T gx = C[l * n2 + p], gy = B[l * n2 + p], gzl = gz[l];
+      const T hs = h + (gx + gy + gzl);
+      const T t = (gx * gx + gy * gy + gzl * gzl) / hs;
+      const T w = w01 * gauss.w[l];
+      g[0][l] = w * (hs - T(2) * gx + t);
+      g[1][l] = w * (hs - T(2) * gy + t);
+      g[2][l] = w * (hs - T(2) * gzl + t);
+      g[3][l] = w * (t - gx - gy);
+      g[4][l] = w * (t - gx - gzl);
+      g[5][l] = w * (t - gy - gzl);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+#pragma unroll
+      for (int l = 0; l < n; ++l) g[c][l] = T(0);
+  }
+  cell_sync<WL>();
+}
+
+// The lane's z-line of a field of node values without the Dirichlet mask (geometry data);
+// inactive lanes read zero.
+template <int N, typename T>
+__device__ __forceinline__ void gather_zline_nodes(const CellCtx &cc, const T *__restrict__ v, T (&u)[N]) {
+#pragma unroll
+  for (int l = 0; l < N; ++l) u[l] = cc.active ? v[cc.base + cc.plane * l] : T(0);
+}
+
+// ---------------------------------------------------------------------------------------
 // Brick apply kernel.
 
 // Raw buffer resource at p (no stride, 2^31 - 1 bytes in range, 32-bit data format).
@@ -416,7 +508,9 @@ __device__ __forceinline__ int halo_index(int X, int Y, int Z, int MX, int MY, i
 // brick (x fastest, then y, then z; chunks outside the mesh are skipped); every lane holds
 // the src line (and, on curved meshes, the metric and kappa) of its cell of the next chunk
 // in registers, loaded while the current chunk is computed.
-template <int K, typename T, bool CURVED, int SHAPE>
+// OTF (curved only): `metric` holds the node displacements of the level (one value per DoF)
+// and the metric is formed on the fly (otf_metric); otherwise the stored per-point metric.
+template <int K, typename T, bool CURVED, int SHAPE, bool OTF = false>
 __global__ void __launch_bounds__(kBlock)
 apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ halo,
                    const T *__restrict__ kappa, const T *__restrict__ metric, BrickGrid bg, T h) {
@@ -526,8 +620,12 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
   cell_at(0, 0, 0, cc, cell);
   T u[n];
   T g[6][CURVED ? n : 1];
+  T dz[OTF ? n : 1];   // on the fly: the node displacements of the lane's z-line
   gather_zline(cc, src, u);
-  if constexpr (CURVED) load_metric<n, kStreamMetric<K, T>>(cc.active, metric + cell * (6 * n3), p, g);
+  if constexpr (CURVED && OTF)
+    gather_zline_nodes(cc, metric, dz);
+  else if constexpr (CURVED)
+    load_metric<n, kStreamMetric<K, T>>(cc.active, metric + cell * (6 * n3), p, g);
   T kap = cc.active ? kappa[cell] : T(0);
 
 #pragma unroll
@@ -542,7 +640,15 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
     int64_t celln;
     cell_at(nx, ny, nz, cn, celln);
     double *ctile = tile + ((jz * BZ + lz) * K) * (TX * TY) + ((jy * BY + ly) * K) * TX + (jx * CX + lx) * K;
-    if constexpr (CURVED) {
+    if constexpr (CURVED && OTF) {
+      otf_metric<K, T, WL>(cc, dz, A, B, C, eo, h, g);
+      curved_cell<K, T, TX, TY, WL>(
+          cc, u, g, kap, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
+          [&] {
+            gather_zline_nodes(cn, metric, dz);
+            kap = cn.active ? kappa[celln] : T(0);
+          });
+    } else if constexpr (CURVED) {
       curved_cell<K, T, TX, TY, WL>(
           cc, u, g, kap, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
           [&] {
@@ -818,7 +924,8 @@ cheb_halo_kernel(const T *__restrict__ ax, const T *__restrict__ halo, const T *
 
 // ---------------------------------------------------------------------------------------
 // Per-cell gradient kernel: g_c = -lambda_c^T A_c^{(kappa=1)} u_c (CPB cells per group).
-template <int K, typename T, bool CURVED>
+// OTF: `metric` holds the node displacements and the metric is formed on the fly.
+template <int K, typename T, bool CURVED, bool OTF = false>
 __global__ void __launch_bounds__(kBlock)
 kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restrict__ grad,
                   const T *__restrict__ metric, int Nc, int N1, T h, int dmask) {
@@ -846,7 +953,13 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
   gather_zline(cc, u, ul);
   if constexpr (CURVED) {
     T g[6][n];
-    load_metric<n, false>(active, metric + (active ? cell : 0) * (6 * n3), p, g);
+    if constexpr (OTF) {
+      T dz[n];
+      gather_zline_nodes(cc, metric, dz);
+      otf_metric<K, T, false>(cc, dz, A, B, C, eo, h, g);
+    } else {
+      load_metric<n, false>(active, metric + (active ? cell : 0) * (6 * n3), p, g);
+    }
     curved_cell<K, T>(cc, ul, g, T(1), A, B, C, eo);
   } else {
     cart_cell<K, T>(cc, ul, active ? h : T(0), A, B, A, B, eo);
@@ -987,8 +1100,12 @@ static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, 
   const T *none = nullptr;
   if (c.p.geometry == MFL_GEOM_CURVED) {
     const BrickGrid bg = brick_grid<K, T, true, kShapeDefault>(L.Nc, L.N1, dm);
-    launch_timed(apply_brick_kernel<K, T, true, kShapeDefault>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src, dst,
-                 halo, kappa, metric, bg, T(L.h));
+    if (metric_on_the_fly(c.p))
+      launch_timed(apply_brick_kernel<K, T, true, kShapeDefault, true>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src,
+                   dst, halo, kappa, metric, bg, T(L.h));
+    else
+      launch_timed(apply_brick_kernel<K, T, true, kShapeDefault>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src, dst,
+                   halo, kappa, metric, bg, T(L.h));
   } else {
     const int shape = level_shape<K, T, false>(L.Nc);
     if constexpr (TallShape<K, T, false>::tall) {
@@ -1208,11 +1325,11 @@ hipError_t launch_cg_cheb_halo(const Context &c, const Level &L, const void *b, 
 hipError_t launch_cg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
                            hipStream_t s, int dmask, const LaunchEvents *ev) {
   if (dtype == MFL_F64) {
-#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s, dmask, ev)
+#define CASE(K) return cg_apply_k<K, double>(c, L, c.tab64, L.kappa64, metric_on_the_fly(c.p) ? L.disp64 : L.metric64, (const double *)src, (double *)dst, (double *)L.halo, s, dmask, ev)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   } else {
-#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s, dmask, ev)
+#define CASE(K) return cg_apply_k<K, float>(c, L, c.tab32, L.kappa32, metric_on_the_fly(c.p) ? L.disp32 : L.metric32, (const float *)src, (float *)dst, (float *)L.halo, s, dmask, ev)
     MFL_DISPATCH_K(c.k, CASE)
 #undef CASE
   }
@@ -1239,7 +1356,9 @@ static hipError_t kappa_grad_k(const Context &c, const Level &L, const double *u
   constexpr int CPB = Shape<K>::cpb;
   const int grid = int((L.ncells + CPB - 1) / CPB);
   const int dir = dirichlet_mask(c.p);
-  if (c.p.geometry == MFL_GEOM_CURVED)
+  if (c.p.geometry == MFL_GEOM_CURVED && metric_on_the_fly(c.p))
+    kappa_grad_kernel<K, double, true, true><<<grid, kBlock, 0, s>>>(u, lam, grad, L.disp64, L.Nc, L.N1, L.h, dir);
+  else if (c.p.geometry == MFL_GEOM_CURVED)
     kappa_grad_kernel<K, double, true><<<grid, kBlock, 0, s>>>(u, lam, grad, L.metric64, L.Nc, L.N1, L.h, dir);
   else
     kappa_grad_kernel<K, double, false><<<grid, kBlock, 0, s>>>(u, lam, grad, nullptr, L.Nc, L.N1, L.h, dir);

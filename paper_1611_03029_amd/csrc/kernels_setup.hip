@@ -161,6 +161,103 @@ diag_curved_kernel(double *__restrict__ diag, const double *__restrict__ kappa,
   }
 }
 
+// Node displacements d = amp sin(pi x) sin(pi y) sin(pi z) of the curved map x = X + d (1,1,1)
+// at the CG nodes of a level (node coordinates and product order of metric_kernel), in FP64
+// and FP32: the geometry data of the on-the-fly metric.
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+disp_kernel(double *__restrict__ d64, float *__restrict__ d32, int Nc, int N1, double h, double amp,
+            Tab<K + 1, double> tb) {
+  const int64_t total = int64_t(N1) * N1 * N1;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    const int g[3] = {int(i % N1), int((i / N1) % N1), int(i / (int64_t(N1) * N1))};
+    double sn[3];
+    for (int e = 0; e < 3; ++e) {
+      const int c = min(g[e] / K, Nc - 1);
+      sn[e] = sin(M_PI * ((c + tb.gll[g[e] - c * K]) * h));
+    }
+    const double v = amp * sn[0] * sn[1] * sn[2];
+    d64[i] = v;
+    d32[i] = float(v);
+  }
+}
+
+// Setup-time metric of one cell from its node displacements (one work-group per cell, direct
+// tensor sums): with g = grad d at Gauss point q and s = g . (1,1,1), J = h I + (1,1,1) g^T,
+// det J = h^2 (h + s) and G = w [(h + s) I - (1 g^T + g 1^T) + |g|^2 / (h + s) 1 1^T], stored to
+// G[e n^3 + q] (e: 00, 11, 22, 01, 02, 12).  Raises kFlagDetJ for a determinant that is not
+// positive or not finite.  dl: the cell's n^3 displacements (local lexicographic).
+template <int K>
+__device__ void otf_cell_metric(const double *dl, double *G, const double *S, const double *Sd, const double *w,
+                                double h, int *flag) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  for (int q = threadIdx.x; q < n3; q += kBlock) {
+    const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+    double g[3] = {0, 0, 0};
+    for (int i2 = 0; i2 < n; ++i2)
+      for (int i1 = 0; i1 < n; ++i1)
+        for (int i0 = 0; i0 < n; ++i0) {
+          const double di = dl[i0 + n * (i1 + n * i2)];
+          g[0] += di * Sd[q0 * n + i0] * S[q1 * n + i1] * S[q2 * n + i2];
+          g[1] += di * S[q0 * n + i0] * Sd[q1 * n + i1] * S[q2 * n + i2];
+          g[2] += di * S[q0 * n + i0] * S[q1 * n + i1] * Sd[q2 * n + i2];
+        }
+    const double hs = h + (g[0] + g[1] + g[2]);
+    const double det = h * h * hs;
+    if (!(det > 0.0) || !isfinite(det)) atomicOr(flag, int(kFlagDetJ));
+    const double t = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / hs;
+    const double wq = w[q0] * w[q1] * w[q2];
+    G[0 * n3 + q] = wq * (hs - 2.0 * g[0] + t);
+    G[1 * n3 + q] = wq * (hs - 2.0 * g[1] + t);
+    G[2 * n3 + q] = wq * (hs - 2.0 * g[2] + t);
+    G[3 * n3 + q] = wq * (t - g[0] - g[1]);
+    G[4 * n3 + q] = wq * (t - g[0] - g[2]);
+    G[5 * n3 + q] = wq * (t - g[1] - g[2]);
+  }
+}
+
+// One work-group per curved cell with the on-the-fly metric: the Jacobian check at setup
+// (diag == nullptr) or, in addition, the cell's contributions to diag(A) as in
+// diag_curved_kernel.
+template <int K>
+__global__ void __launch_bounds__(kBlock)
+otf_cell_kernel(double *__restrict__ diag, const double *__restrict__ kappa, const double *__restrict__ disp,
+                int Nc, int N1, double h, int dmask, int *__restrict__ flag, Tab<K + 1, double> tb) {
+  constexpr int n = K + 1, n3 = n * n * n;
+  __shared__ double S[n * n], Sd[n * n], w[n], dl[n3], G[6 * n3];
+  for (int i = threadIdx.x; i < n * n; i += kBlock) {
+    S[i] = tb.S[i];
+    Sd[i] = tb.Sd[i];
+  }
+  if (threadIdx.x < n) w[threadIdx.x] = tb.w[threadIdx.x];
+  const int64_t cell = blockIdx.x;
+  const int cx = int(cell % Nc), cy = int((cell / Nc) % Nc), cz = int(cell / (int64_t(Nc) * Nc));
+  const int64_t plane = int64_t(N1) * N1;
+  for (int i = threadIdx.x; i < n3; i += kBlock) {
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    dl[i] = disp[(cx * K + a) + N1 * int64_t(cy * K + b) + plane * (cz * K + l)];
+  }
+  __syncthreads();
+  otf_cell_metric<K>(dl, G, S, Sd, w, h, flag);
+  if (!diag) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += kBlock) {
+    const int a = i % n, b = (i / n) % n, l = i / (n * n);
+    const int gx = cx * K + a, gy = cy * K + b, gz = cz * K + l;
+    if (dirichlet_dof(gx, gy, gz, N1, dmask)) continue;
+    double acc = 0;
+    for (int q = 0; q < n3; ++q) {
+      const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+      const double d0 = Sd[q0 * n + a] * S[q1 * n + b] * S[q2 * n + l];
+      const double d1 = S[q0 * n + a] * Sd[q1 * n + b] * S[q2 * n + l];
+      const double d2 = S[q0 * n + a] * S[q1 * n + b] * Sd[q2 * n + l];
+      acc += G[q] * d0 * d0 + G[n3 + q] * d1 * d1 + G[2 * n3 + q] * d2 * d2 +
+             2.0 * (G[3 * n3 + q] * d0 * d1 + G[4 * n3 + q] * d0 * d2 + G[5 * n3 + q] * d1 * d2);
+    }
+    atomic_add(diag + gx + N1 * int64_t(gy) + plane * gz, kappa[cell] * acc);
+  }
+}
+
 // f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z): the forcing of u = sin sin sin.
 struct SineForcing {
   __device__ double operator()(const double x[3]) const {
@@ -333,6 +430,18 @@ inline int grid_for(int64_t items, int cap = 65536) {
 
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s) {
   const int64_t items = L.ncells * int64_t(c.n) * c.n * c.n;
+  if (metric_on_the_fly(c.p)) {
+    // node displacements, then the Jacobian check of every cell
+#define CASE(K)                                                                                  \
+  disp_kernel<K><<<grid_for(L.ndofs), kBlock, 0, s>>>(L.disp64, L.disp32, L.Nc, L.N1, L.h, c.p.curve_amp, \
+                                                      shrink_tab<K + 1, double>(c.tab64));       \
+  otf_cell_kernel<K><<<int(L.ncells), kBlock, 0, s>>>(nullptr, nullptr, L.disp64, L.Nc, L.N1, L.h, 0, c.flags, \
+                                                      shrink_tab<K + 1, double>(c.tab64));       \
+  break
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+    return hipGetLastError();
+  }
 #define CASE(K)                                                                                \
   metric_kernel<K><<<grid_for(items), kBlock, 0, s>>>(                                          \
       L.metric64, L.metric32, L.Nc, L.h, c.p.curve_amp, c.p.kappa_field == MFL_KAPPA_COSINE,        \
@@ -348,7 +457,14 @@ hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s) {
   const int dir = dirichlet_mask(c.p);
   hipError_t e = launch_fill(L.diag64, MFL_F64, L.ndofs, 0.0, s);
   if (e != hipSuccess) return e;
-  if (c.p.geometry == MFL_GEOM_CURVED) {
+  if (c.p.geometry == MFL_GEOM_CURVED && metric_on_the_fly(c.p)) {
+#define CASE(K)                                                                                  \
+  otf_cell_kernel<K><<<int(L.ncells), kBlock, 0, s>>>(L.diag64, L.kappa64, L.disp64, L.Nc, L.N1, L.h, dir, \
+                                                      c.flags, shrink_tab<K + 1, double>(c.tab64)); \
+  break
+    MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  } else if (c.p.geometry == MFL_GEOM_CURVED) {
 #define CASE(K)                                                                                  \
   diag_curved_kernel<K><<<grid_for(items), kBlock, 0, s>>>(L.diag64, L.kappa64, L.metric64, L.Nc, \
                                                            L.N1, dir, shrink_tab<K + 1, double>(c.tab64)); \

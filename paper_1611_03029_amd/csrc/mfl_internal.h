@@ -92,8 +92,10 @@ struct Level {
   double h = 0.0;
   double *kappa64 = nullptr;
   float *kappa32 = nullptr;
-  double *metric64 = nullptr;   // curved: [cell][6][n^3], w_q det J J^{-1} J^{-T}
+  double *metric64 = nullptr;   // curved, stored metric: [cell][6][n^3], w_q det J J^{-1} J^{-T}
   float *metric32 = nullptr;
+  double *disp64 = nullptr;     // curved, metric on the fly: node displacement d (x = X + d (1,1,1)),
+  float *disp32 = nullptr;      // one value per CG DoF (lexicographic)
   double *diag64 = nullptr;
   double *dinv64 = nullptr;
   float *diag32 = nullptr;
@@ -134,6 +136,13 @@ struct Context {
   int prof_used = 0;
   std::vector<hipEvent_t> prof_start, prof_stop;
 };
+
+// Whether the curved metric is formed on the fly (metric_mode AUTO resolves to it with a
+// cellwise kappa).
+inline bool metric_on_the_fly(const mfl_params &p) {
+  return p.disc == MFL_DISC_CG && p.geometry == MFL_GEOM_CURVED && p.kappa_field == MFL_KAPPA_CELLWISE &&
+         p.metric_mode != MFL_METRIC_STORED;
+}
 
 // Face mask of the Dirichlet conditions: bit 0 the lower faces (x_e = domain_lo), bit 1
 // the upper faces (x_e = domain_lo + domain_len).

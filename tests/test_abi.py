@@ -44,9 +44,16 @@ def test_query_dof_counts(k, Nc, disc, dofs):
 
 def test_workspace_scales_with_geometry_and_multigrid():
     cart = mfl.query(mfl.make_params(4, 64))[2]
-    curved = mfl.query(mfl.make_params(4, 64, geometry=mfl.CURVED))[2]
-    # curved: FP64 + FP32 copies of 6 metric entries per quadrature point
+    curved = mfl.query(mfl.make_params(4, 64, geometry=mfl.CURVED, metric_mode=mfl.METRIC_STORED))[2]
+    # stored metric: FP64 + FP32 copies of 6 metric entries per quadrature point
     assert curved - cart >= 262144 * 125 * 6 * 12
+    # on the fly: FP64 + FP32 node displacements only (one value per DoF)
+    otf = mfl.query(mfl.make_params(4, 64, geometry=mfl.CURVED, metric_mode=mfl.METRIC_ON_THE_FLY))[2]
+    assert 257 ** 3 * 12 <= otf - cart < 257 ** 3 * 12 + 4096
+    assert mfl.query(mfl.make_params(4, 64, geometry=mfl.CURVED))[2] == otf   # AUTO, cellwise kappa
+    cos = mfl.query(mfl.make_params(4, 64, geometry=mfl.CURVED, kappa_field=mfl.KAPPA_COSINE))[2]
+    assert cos == curved                                                       # AUTO, kappa field
+    assert mfl.query(mfl.make_params(4, 64, metric_mode=mfl.METRIC_STORED))[2] == cart   # Cartesian: no metric
     mg = mfl.query(mfl.make_params(4, 64, build_mg=True))[2]
     assert mg > cart
 
@@ -69,6 +76,9 @@ def test_workspace_scales_with_geometry_and_multigrid():
                                 dict(kappa_field=mfl.KAPPA_COSINE, geometry=mfl.CURVED, kappa_field_amp=-1.0),
                                 dict(kappa_field=mfl.KAPPA_COSINE, geometry=mfl.CURVED,
                                      kappa_field_amp=float("inf")),
+                                dict(metric_mode=3), dict(metric_mode=-1),
+                                dict(geometry=mfl.CURVED, kappa_field=mfl.KAPPA_COSINE,
+                                     metric_mode=mfl.METRIC_ON_THE_FLY),
                                 dict(degree=8, cells_per_dim=4, build_mg=True, min_level_cells=4),
                                 dict(degree=7, cells_per_dim=4, build_mg=True, min_level_cells=4,
                                      disc=mfl.SIPG)])
@@ -126,6 +136,7 @@ def test_default_kappa_field():
     p = _mfl.Params()
     assert mfl.lib().mfl_default_params(ctypes.byref(p)) == 0
     assert p.kappa_field == mfl.KAPPA_CELLWISE and p.kappa_field_amp == 1e6
+    assert p.metric_mode == mfl.METRIC_AUTO
 
 
 @pytest.mark.parametrize("bad", ["cpu", "dtype", "size", "strided", "not_tensor"])
