@@ -381,9 +381,22 @@ __device__ __forceinline__ void curved_cell(const CellCtx &cc, const T (&u)[K + 
 // lane in 5 phases) from the lane's z-line d of node displacements, and returns the metric
 // of the lane's z-line of Gauss points in the layout of load_metric (00, 11, 22, 01, 02, 12).
 // Buffers A..C are free again when it returns.
+// 1 / x from the hardware reciprocal estimate refined by Newton steps (two in FP64, one in
+// FP32), each of which squares the relative error; within an ulp or two of the division.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// scale multiplies the metric (the cell's kappa, so that the operator phases take kappa 1).
 template <int K, typename T, bool WL>
 __device__ __forceinline__ void otf_metric(const CellCtx &cc, const T (&d)[K + 1], T *A, T *B, T *C,
-                                           const EOTab<K + 1, T> &eo, T h, T (&g)[6][K + 1]) {
+                                           const EOTab<K + 1, T> &eo, T h, T scale, T (&g)[6][K + 1]) {
   constexpr int n = K + 1, n2 = n * n;
   constexpr const ct::DGTab<n, T> &gauss = ct::DGTables<n, T>::tab;   // Gauss weights w
   const int i0 = cc.i0, i1 = cc.i1, p = i0 + n * i1;
@@ -430,19 +443,20 @@ __device__ __forceinline__ void otf_metric(const CellCtx &cc, const T (&d)[K + 1
 #pragma unroll
     for (int l = 0; l < n; ++l) r[l] = A[l * n2 + p];
     eo_apply<n, -1>(eo.D, r, gz);
-    const T w01 = gauss.w[i0] * gauss.w[i1];
+    const T w01 = gauss.w[i0] * gauss.w[i1] * scale;
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       const T gx = C[l * n2 + p], gy = B[l * n2 + p], gzl = gz[l];
       const T hs = h + (gx + gy + gzl);
-      const T t = (gx * gx + gy * gy + gzl * gzl) / hs;
+      const T t = (gx * gx + gy * gy + gzl * gzl) * recip(hs);
       const T w = w01 * gauss.w[l];
-      g[0][l] = w * (hs - T(2) * gx + t);
-      g[1][l] = w * (hs - T(2) * gy + t);
-      g[2][l] = w * (hs - T(2) * gzl + t);
-      g[3][l] = w * (t - gx - gy);
-      g[4][l] = w * (t - gx - gzl);
-      g[5][l] = w * (t - gy - gzl);
+      const T wx = w * gx, wy = w * gy, wz = w * gzl, wd = w * (hs + t), wt = w * t;
+      g[0][l] = wd - T(2) * wx;
+      g[1][l] = wd - T(2) * wy;
+      g[2][l] = wd - T(2) * wz;
+      g[3][l] = wt - wx - wy;
+      g[4][l] = wt - wx - wz;
+      g[5][l] = wt - wy - wz;
     }
   } else {
 #pragma unroll
@@ -641,9 +655,10 @@ apply_brick_kernel(const T *__restrict__ src, T *__restrict__ dst, T *__restrict
     cell_at(nx, ny, nz, cn, celln);
     double *ctile = tile + ((jz * BZ + lz) * K) * (TX * TY) + ((jy * BY + ly) * K) * TX + (jx * CX + lx) * K;
     if constexpr (CURVED && OTF) {
-      otf_metric<K, T, WL>(cc, dz, A, B, C, eo, h, g);
+      otf_metric<K, T, WL>(cc, dz, A, B, C, eo, h, kap, g);   // kappa folded into the metric
+      const T one = T(1);
       curved_cell<K, T, TX, TY, WL>(
-          cc, u, g, kap, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
+          cc, u, g, one, A, B, C, eo, ctile, [&] { gather_zline(cn, src, u); },
           [&] {
             gather_zline_nodes(cn, metric, dz);
             kap = cn.active ? kappa[celln] : T(0);
@@ -956,7 +971,7 @@ kappa_grad_kernel(const T *__restrict__ u, const T *__restrict__ lam, T *__restr
     if constexpr (OTF) {
       T dz[n];
       gather_zline_nodes(cc, metric, dz);
-      otf_metric<K, T, false>(cc, dz, A, B, C, eo, h, g);
+      otf_metric<K, T, false>(cc, dz, A, B, C, eo, h, T(1), g);
     } else {
       load_metric<n, false>(active, metric + (active ? cell : 0) * (6 * n3), p, g);
     }
