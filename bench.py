@@ -625,8 +625,8 @@ def summarize_stats(path, title, command, out_path, top=25):
 
 
 # How each committed summary under profiles/ is made: the rocprofv3 runs (R = repository
-# root on the GPU machine, outputs under gpurun_out/) and the reduction that turns their CSV
-# output into the summary (`python bench.py --reduce NAME DIR [DIR]`).
+# root on the GPU machine, OUT = a directory for their output) and the reduction that turns
+# their CSV output into the summary (`python bench.py --reduce NAME DIR [DIR]`).
 _BENCH_Q4 = "python3 $R/bench.py --steps 5 --warmup 1 --no-extras --no-cpu-baseline"
 _SQ = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
        "SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT")
@@ -638,58 +638,58 @@ REDUCTIONS = {
     "cg_apply_traffic": {
         "out": "profiles/cg_apply_q4_64cubed_curved_traffic.json",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
-                 "-d $R/gpurun_out/pmc_fetch -o run -- " + _BENCH_Q4,
+                 "-d $OUT/pmc_fetch -o run -- " + _BENCH_Q4,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
-                 "-d $R/gpurun_out/pmc_write -o run -- " + _BENCH_Q4]},
+                 "-d $OUT/pmc_write -o run -- " + _BENCH_Q4]},
     "cg_apply_sq": {
         "out": "profiles/cg_apply_q4_64cubed_curved_sq_counters.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ + " --output-format csv "
-                 "-d $R/gpurun_out/pmc_sq -o run -- " + _BENCH_Q4]},
+                 "-d $OUT/pmc_sq -o run -- " + _BENCH_Q4]},
     "cg_solve_sq": {
         "out": "profiles/gmg_pcg_q4_64cubed_sq_counters.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ + " --output-format csv "
-                 "-d $R/gpurun_out/solve_sq -o run -- " + _SOLVE_Q4,
+                 "-d $OUT/solve_sq -o run -- " + _SOLVE_Q4,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ2 + " --output-format csv "
-                 "-d $R/gpurun_out/solve_sq2 -o run -- " + _SOLVE_Q4]},
+                 "-d $OUT/solve_sq2 -o run -- " + _SOLVE_Q4]},
     "cg_solve_traffic": {
         "out": "profiles/gmg_pcg_q4_64cubed_traffic.json",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
-                 "-d $R/gpurun_out/solve_fetch -o run -- " + _SOLVE_Q4,
+                 "-d $OUT/solve_fetch -o run -- " + _SOLVE_Q4,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
-                 "-d $R/gpurun_out/solve_write -o run -- " + _SOLVE_Q4]},
+                 "-d $OUT/solve_write -o run -- " + _SOLVE_Q4]},
     "cg_solve_stats": {
         "out": "profiles/gmg_pcg_q4_64cubed_kernel_stats.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-                 "-d $R/gpurun_out/solve_ktrace -o run -- " + _SOLVE_Q4]},
+                 "-d $OUT/solve_ktrace -o run -- " + _SOLVE_Q4]},
     "sipg_sq": {
         "out": "profiles/sipg_apply_q3_q5_sq_counters.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ + " --output-format csv "
-                 "-d $R/gpurun_out/sipg_sq -o run -- " + _SIPG,
+                 "-d $OUT/sipg_sq -o run -- " + _SIPG,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _SQ2 + " --output-format csv "
-                 "-d $R/gpurun_out/sipg_sq2 -o run -- " + _SIPG,
+                 "-d $OUT/sipg_sq2 -o run -- " + _SIPG,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + _TCC + " --output-format csv "
-                 "-d $R/gpurun_out/sipg_tcc -o run -- " + _SIPG]},
+                 "-d $OUT/sipg_tcc -o run -- " + _SIPG]},
     "sipg_stats": {
         "out": "profiles/sipg_apply_q3_q5_kernel_stats.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-                 "-d $R/gpurun_out/sipg_ktrace -o run -- python3 $R/bench.py --sipg-only --steps 20"]},
+                 "-d $OUT/sipg_ktrace -o run -- python3 $R/bench.py --sipg-only --steps 20"]},
     "sipg_traffic": {
         "out": "profiles/sipg_apply_q3_q5_traffic.json",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
-                 "-d $R/gpurun_out/sipg_fetch -o run -- " + _SIPG,
+                 "-d $OUT/sipg_fetch -o run -- " + _SIPG,
                  "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
-                 "-d $R/gpurun_out/sipg_write -o run -- " + _SIPG]},
+                 "-d $OUT/sipg_write -o run -- " + _SIPG]},
     "cg_apply_stats": {
         "out": "profiles/cg_apply_q4_64cubed_curved_kernel_stats.txt",
         "runs": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-                 "-d $R/gpurun_out/prof_ktrace -o run -- python3 $R/bench.py --steps 20 --warmup 2 "
+                 "-d $OUT/prof_ktrace -o run -- python3 $R/bench.py --steps 20 --warmup 2 "
                  "--no-extras --no-cpu-baseline"]},
 }
 
 
 def run_reduction(name, dirs):
     spec = REDUCTIONS[name]
-    cmd = " ; ".join(spec["runs"]) + "  (R = repository root)"
+    cmd = " ; ".join(spec["runs"]) + "  (R = repository root, OUT = output directory)"
     out = os.path.join(ROOT, spec["out"])
     if name == "cg_apply_traffic":
         n, cells, q = 257 ** 3, 64 ** 3, 125
