@@ -169,7 +169,33 @@ struct ColumnOrder {
     cx = x0 + r - (r / tx) * tx;
     return true;
   }
+  // the x range [x0, x1) of the XCD's tile: consecutive positions of the traversal are
+  // x-neighbours unless a row of the tile ends between them
+  __device__ static void xrange(int xcd, int Nc, int &x0, int &x1) {
+    const int ix = xcd % SX;
+    x0 = ix * Nc / SX;
+    x1 = (ix + 1) * Nc / SX;
+  }
 };
+
+// Whether the x-neighbour of the cell in slot lc lies in slot lc - 1 (left) or lc + 1
+// (right) of the same work-group, so that its values can be read from the work-group's LDS
+// copy after the first phase (the phases are separated by work-group barriers).  Used where
+// cells straddle wavefronts (not WL): measured 3-6% faster there (k = 4, 5); with
+// wavefront-local cells (k <= 3) the neighbour would have to lie in the lane's wavefront,
+// and the branches cost more than the loads they save (k = 3 FP32 5% slower).
+template <bool WL>
+__device__ __forceinline__ void lds_x_neighbours(bool active, int lc, int cpb, int cx, int Nc, bool &lin,
+                                                 bool &rin) {
+  if constexpr (WL) {
+    lin = rin = false;
+  } else {
+    int x0, x1;
+    ColumnOrder::xrange(blockIdx.x % 8, Nc, x0, x1);
+    lin = active && lc > 0 && cx > x0;
+    rin = active && lc + 1 < cpb && cx + 1 < x1;
+  }
+}
 
 // A lane's x-line of a DG vector: its n values are contiguous (local lexicographic order,
 // x fastest).  For even n every x-line starts at an even element offset, so on 16-byte
@@ -310,8 +336,20 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
     const int o = i1 * n2 + i0 * n, ol = i1 * PS + i0 * n;
     const T *pl = src + (hasL ? cell - 1 : cell) * n3 + o, *pr = src + (hasR ? cell + 1 : cell) * n3 + o;
     constexpr bool VX = sizeof(T) == 8;
-    load_xline<n, VX>(pl, ul);
-    load_xline<n, VX>(pr, ur);
+    bool lin, rin;
+    lds_x_neighbours<WL>(active, lc, CPB, cx, Nc, lin, rin);
+    if (lin) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) ul[a] = U[(slot - 1) * CS + ol + a];
+    } else {
+      load_xline<n, VX>(pl, ul);
+    }
+    if (rin) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) ur[a] = U[(slot + 1) * CS + ol + a];
+    } else {
+      load_xline<n, VX>(pr, ur);
+    }
 #pragma unroll
     for (int a = 0; a < n; ++a) u[a] = Uc[ol + a];
     sipg_line<n, T>(tb, u, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
@@ -722,8 +760,20 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
     const bool hasL = cx > 0, hasR = cx < Nc - 1;
     const int o = i1 * n2 + i0 * n;
     const T *pl = src + (hasL ? cell - 1 : cell) * n3 + o, *pr = src + (hasR ? cell + 1 : cell) * n3 + o;
-    load_xline<n>(pl, ul);
-    load_xline<n>(pr, ur);
+    bool lin, rin;
+    lds_x_neighbours<WL>(active, lc, CPB, cx, Nc, lin, rin);
+    if (lin) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) ul[a] = U[(slot - 1) * n3 + o + a];
+    } else {
+      load_xline<n>(pl, ul);
+    }
+    if (rin) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) ur[a] = U[(slot + 1) * n3 + o + a];
+    } else {
+      load_xline<n>(pr, ur);
+    }
     load_xline<n>(b + xl0, w);
 #pragma unroll
     for (int a = 0; a < n; ++a) v[a] = Uc[o + a];
@@ -731,18 +781,20 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
 #pragma unroll
     for (int a = 0; a < n; ++a) w[a] -= Rc[i1 * n2 + i0 * n + a] + out[a];
     eo_apply_t<n, 1>(eo.S, w, r);
+    // into R (the lane's own x-line, read above): U keeps the cell's values for the
+    // x-neighbours that read them in this phase
 #pragma unroll
-    for (int a = 0; a < n; ++a) Uc[i1 * n2 + i0 * n + a] = r[a];
+    for (int a = 0; a < n; ++a) Rc[i1 * n2 + i0 * n + a] = r[a];
   }
   cell_sync<WL>();
   // S^T along y
   if (inblk) {
     T w[n], r[n];
 #pragma unroll
-    for (int j = 0; j < n; ++j) w[j] = Uc[i1 * n2 + j * n + i0];
+    for (int j = 0; j < n; ++j) w[j] = Rc[i1 * n2 + j * n + i0];
     eo_apply_t<n, 1>(eo.S, w, r);
 #pragma unroll
-    for (int j = 0; j < n; ++j) Rc[i1 * n2 + j * n + i0] = r[j];
+    for (int j = 0; j < n; ++j) Uc[i1 * n2 + j * n + i0] = r[j];
   }
   cell_sync<WL>();
   // S^T along z, D'^{-1}, S along z
@@ -750,7 +802,7 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
     T w[n], r[n], dp[n];
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-      w[l] = Rc[l * n2 + p];
+      w[l] = Uc[l * n2 + p];
       dp[l] = dpinv[cell * n3 + l * n2 + p];
     }
     eo_apply_t<n, 1>(eo.S, w, r);
@@ -758,17 +810,17 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
     for (int l = 0; l < n; ++l) r[l] *= dp[l];
     eo_apply<n, 1>(eo.S, r, w);
 #pragma unroll
-    for (int l = 0; l < n; ++l) Uc[l * n2 + p] = w[l];
+    for (int l = 0; l < n; ++l) Rc[l * n2 + p] = w[l];
   }
   cell_sync<WL>();
   // S along y
   if (inblk) {
     T w[n], r[n];
 #pragma unroll
-    for (int j = 0; j < n; ++j) w[j] = Uc[i1 * n2 + j * n + i0];
+    for (int j = 0; j < n; ++j) w[j] = Rc[i1 * n2 + j * n + i0];
     eo_apply<n, 1>(eo.S, w, r);
 #pragma unroll
-    for (int j = 0; j < n; ++j) Rc[i1 * n2 + j * n + i0] = r[j];
+    for (int j = 0; j < n; ++j) Uc[i1 * n2 + j * n + i0] = r[j];
   }
   cell_sync<WL>();
   // S along x and the update of the lane's x-line (d is read in full before any store: a
@@ -776,7 +828,7 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
   if (active) {
     T w[n], cw[n], dn[n], xn[n];
 #pragma unroll
-    for (int a = 0; a < n; ++a) w[a] = Rc[i1 * n2 + i0 * n + a];
+    for (int a = 0; a < n; ++a) w[a] = Uc[i1 * n2 + i0 * n + a];
     load_xline<n>(d + xl0, dn);
     eo_apply<n, 1>(eo.S, w, cw);
 #pragma unroll
