@@ -52,6 +52,20 @@ def test_curved_apply_matches_oracle(k, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("k,Nc", [(2, 6), (4, 4)])
+def test_curved_mixed_conditions_match_oracle(k, Nc, mode):
+    """Neumann lower faces (the node displacements there are not masked: the geometry is not
+    a Dirichlet datum) and Dirichlet upper faces, FP64 and FP32."""
+    box = Box(Nc, k, 0.1)
+    kap = kappa_field(box.n_cells)
+    prob = mfl.Problem(k, Nc, kappa=kap, geometry=mfl.CURVED, curve_amp=0.1, bc=mfl.MIXED, metric_mode=mode)
+    u = uniform_vector(box.n_dofs, 50 + k)
+    ref = o_cg.assemble(box, kap, bc="mixed") @ u
+    assert rel_err(prob.apply(t(u)), ref) <= 1e-12
+    assert rel_err(prob.apply(t(u, torch.float32)).double(), ref) <= 2e-5
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_curved_diagonal_and_gradient_match_oracle(mode):
     k, Nc = 3, 4
     box = Box(Nc, k, 0.1)
