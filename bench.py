@@ -714,8 +714,8 @@ def run_reduction(name, dirs):
         fine = 8192 * 256   # work-items of the 64^3 level's operator launch (8192 bricks)
         groups = [("apply_brick_kernel<4, double, false", "Cartesian operator, FP64, 64^3 level", fine),
                   ("apply_brick_kernel<4, float, false", "Cartesian operator, FP32, 64^3 level", fine),
-                  ("cheb_halo_kernel<4, double>", "Chebyshev update + halo, FP64, 64^3 level", 2097152),
-                  ("cheb_halo_kernel<4, float>", "Chebyshev update + halo, FP32, 64^3 level", 2097152),
+                  ("cheb_halo_quad_kernel<4, double>", "Chebyshev update + halo, FP64, 64^3 level", fine),
+                  ("cheb_halo_quad_kernel<4, float>", "Chebyshev update + halo, FP32, 64^3 level", fine),
                   ("restrict_cell_kernel<4, double, 2>", "restriction, rows of 2 cells, FP64, 64^3 level"),
                   ("restrict_cell_kernel<4, float, 4>", "restriction, rows of 4 cells, FP32, 64^3 level"),
                   ("prolongate_kernel<4, double, double, 6>", "prolongation, rows of 6 cells, FP64, 64^3 level"),
@@ -731,10 +731,12 @@ def run_reduction(name, dirs):
                                                            "grid": 8192 * 256, "algorithmic_bytes": 16 * n},
                 "apply_brick_kernel<4,float,cartesian>": {"match": "apply_brick_kernel<4, float, false",
                                                           "grid": 8192 * 256, "algorithmic_bytes": 8 * n},
-                "cheb_halo_kernel<4,float>": {"match": "cheb_halo_kernel<4, float>", "grid": 2097152,
-                                              "algorithmic_bytes": 28 * n},
-                "cheb_halo_kernel<4,double>": {"match": "cheb_halo_kernel<4, double>", "grid": 2097152,
-                                               "algorithmic_bytes": 56 * n}}
+                # four DoFs per lane only on the 64^3 level (the 32^3 level's one-DoF-per-lane
+                # form has the same grid size and another name)
+                "cheb_halo_quad_kernel<4,float>": {"match": "cheb_halo_quad_kernel<4, float>", "grid": 8192 * 256,
+                                                   "algorithmic_bytes": 28 * n},
+                "cheb_halo_quad_kernel<4,double>": {"match": "cheb_halo_quad_kernel<4, double>", "grid": 8192 * 256,
+                                                    "algorithmic_bytes": 56 * n}}
         reduce_traffic(dirs[0], dirs[1], 8 * n, kern, None,
                        "GMG-PCG solve, CG Q4 on 64^3 Cartesian cells, FP64 and FP32 V-cycles",
                        spec["runs"], out)

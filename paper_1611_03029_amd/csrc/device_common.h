@@ -31,6 +31,32 @@ inline void launch_timed(void (*kernel)(Params...), int grid, int block, hipStre
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 
+// Four consecutive vector entries moved with 16-byte accesses (one for FP32, two for FP64).
+// With one entry per lane a streaming kernel keeps too few bytes in flight per wavefront to
+// cover the HBM latency; four per lane reach the streaming rate.  The pointer plus the
+// index must be 16-byte aligned.
+template <typename T>
+struct alignas(16) Quad {
+  T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(const T *p, int64_t i) {
+  return *reinterpret_cast<const Quad<T> *>(p + i);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_quad(T *p, int64_t i, const Quad<T> &q) {
+  *reinterpret_cast<Quad<T> *>(p + i) = q;
+}
+
+// Host check for the quad kernels: every non-null pointer 16-byte aligned.
+inline bool aligned16() { return true; }
+template <typename P, typename... R>
+inline bool aligned16(P p, R... rest) {
+  return reinterpret_cast<uintptr_t>(p) % 16 == 0 && aligned16(rest...);
+}
+
 // LDS atomic add without return (ds_add_f64 / ds_add_f32)
 template <typename T>
 __device__ __forceinline__ void lds_add(T *p, T v) {

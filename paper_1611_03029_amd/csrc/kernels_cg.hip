@@ -892,49 +892,113 @@ struct DofDiv {
   FastDiv n1, mx, my, mz;
 };
 
+// A x at DoF (gx, gy, gz): the brick kernel's value a plus the halo record entries of the
+// lower bricks sharing the DoF, in the order of halo_add_kernel.
+template <int K, typename T>
+__device__ __forceinline__ T cheb_halo_ax(T a, int gx, int gy, int gz, const T *__restrict__ halo, const BrickGrid &bg,
+                                          const DofDiv &dv, int hs) {
+  const int MX = bg.sx * K, MY = bg.my, MZ = bg.mz;
+  const int g[3] = {gx, gy, gz};
+  const int q[3] = {int(dv.mx.div(gx)), int(dv.my.div(gy)), int(dv.mz.div(gz))};
+  const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
+  int bb[3], X[3];
+  bool sh[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    bb[e] = min(q[e], NB[e] - 1);
+    X[e] = g[e] - bb[e] * M[e];
+    sh[e] = X[e] == 0 && bb[e] > 0;
+  }
+  if (!(sh[0] || sh[1] || sh[2]) || dirichlet_dof(gx, gy, gz, bg.N1, bg.dmask)) return a;
+  auto entry = [&](int m) {
+    const int ob0 = bb[0] - (m & 1), ob1 = bb[1] - ((m >> 1) & 1), ob2 = bb[2] - ((m >> 2) & 1);
+    const int tx = (m & 1) ? MX : X[0], ty = (m & 2) ? MY : X[1], tz = (m & 4) ? MZ : X[2];
+    const int64_t ob = ob0 + int64_t(bg.nbx) * (ob1 + int64_t(bg.nby) * ob2);
+    return ob * hs + halo_index(tx, ty, tz, MX, MY, MZ);
+  };
+  const int m0 = sh[0] ? 1 : (sh[1] ? 2 : 4);
+  T sum = halo[entry(m0)];
+  for (int m = m0 + 1; m < 8; ++m) {
+    if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
+    sum += halo[entry(m)];
+  }
+  return a + sum;
+}
+
 template <int K, typename T>
 __global__ void __launch_bounds__(kBlock)
 cheb_halo_kernel(const T *__restrict__ ax, const T *__restrict__ halo, const T *__restrict__ b,
                  const T *__restrict__ dinv, T *__restrict__ d, T *__restrict__ x,
                  double *__restrict__ x64, BrickGrid bg, DofDiv dv, T c1, T c2) {
-  const int MX = bg.sx * K, MY = bg.my, MZ = bg.mz, N1 = bg.N1;
+  const int N1 = bg.N1;
   const uint32_t n = uint32_t(N1) * uint32_t(N1) * uint32_t(N1);
-  const int hs = halo_size(MX, MY, MZ);
+  const int hs = halo_size(bg.sx * K, bg.my, bg.mz);
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     const uint32_t r = dv.n1.div(i), gz = dv.n1.div(r);
-    const int g[3] = {int(i - r * uint32_t(N1)), int(r - gz * uint32_t(N1)), int(gz)};
-    const int q[3] = {int(dv.mx.div(g[0])), int(dv.my.div(g[1])), int(dv.mz.div(g[2]))};
-    const int M[3] = {MX, MY, MZ}, NB[3] = {bg.nbx, bg.nby, bg.nbz};
-    int bb[3], X[3];
-    bool sh[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      bb[e] = min(q[e], NB[e] - 1);
-      X[e] = g[e] - bb[e] * M[e];
-      sh[e] = X[e] == 0 && bb[e] > 0;
-    }
-    T a = ax[i];
-    if ((sh[0] || sh[1] || sh[2]) && !dirichlet_dof(g[0], g[1], g[2], N1, bg.dmask)) {
-      auto entry = [&](int m) {
-        const int ob0 = bb[0] - (m & 1), ob1 = bb[1] - ((m >> 1) & 1), ob2 = bb[2] - ((m >> 2) & 1);
-        const int tx = (m & 1) ? MX : X[0], ty = (m & 2) ? MY : X[1], tz = (m & 4) ? MZ : X[2];
-        const int64_t ob = ob0 + int64_t(bg.nbx) * (ob1 + int64_t(bg.nby) * ob2);
-        return ob * hs + halo_index(tx, ty, tz, MX, MY, MZ);
-      };
-      const int m0 = sh[0] ? 1 : (sh[1] ? 2 : 4);
-      T sum = halo[entry(m0)];
-      for (int m = m0 + 1; m < 8; ++m) {
-        if (((m & 1) && !sh[0]) || ((m & 2) && !sh[1]) || ((m & 4) && !sh[2])) continue;
-        sum += halo[entry(m)];
-      }
-      a = a + sum;
-    }
+    const int gx = int(i - r * uint32_t(N1)), gy = int(r - gz * uint32_t(N1));
+    const T a = cheb_halo_ax<K, T>(ax[i], gx, gy, int(gz), halo, bg, dv, hs);
     const T dn = c1 * d[i] + c2 * dinv[i] * (b[i] - a);
     const T xn = x[i] + dn;
     d[i] = dn;
     x[i] = xn;
     if (x64) x64[i] = double(xn);
   }
+}
+
+// Quad form of cheb_halo_kernel: four consecutive DoFs per lane, b, A x, D^{-1}, d and x
+// moved in 16-byte accesses (the vectors are 16-byte aligned, checked on the host).  The
+// grid coordinates of the first DoF come from two divisions; the other three follow by
+// stepping along x (at most one of them wraps to the next row).  The halo entries are added
+// per DoF exactly as in cheb_halo_kernel, so the results are the same bit for bit.  The
+// N1^3 mod 4 trailing DoFs are done by the first work-group.
+template <int K, typename T>
+__global__ void __launch_bounds__(kBlock)
+cheb_halo_quad_kernel(const T *__restrict__ ax, const T *__restrict__ halo, const T *__restrict__ b,
+                      const T *__restrict__ dinv, T *__restrict__ d, T *__restrict__ x,
+                      double *__restrict__ x64, BrickGrid bg, DofDiv dv, T c1, T c2) {
+  const int N1 = bg.N1;
+  const uint32_t n = uint32_t(N1) * uint32_t(N1) * uint32_t(N1), nq = n >> 2;
+  const int hs = halo_size(bg.sx * K, bg.my, bg.mz);
+  auto update = [&](T a, T bi, T di, T dd, T xx, T &dn, T &xn) {
+    dn = c1 * dd + c2 * di * (bi - a);
+    xn = xx + dn;
+  };
+  for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nq; c += gridDim.x * kBlock) {
+    const uint32_t i0 = 4 * c;
+    const Quad<T> aq = load_quad(ax, i0), bq = load_quad(b, i0), iq = load_quad(dinv, i0),
+                  dq = load_quad(d, i0), xq = load_quad(x, i0);
+    const uint32_t r = dv.n1.div(i0), gz0 = dv.n1.div(r);
+    const int gx0 = int(i0 - r * uint32_t(N1)), gy0 = int(r - gz0 * uint32_t(N1));
+    Quad<T> dn, xn;
+    Quad<double> x8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int gx = gx0 + j, gy = gy0, gz = int(gz0);
+      if (gx >= N1) {
+        gx -= N1;
+        if (++gy == N1) {
+          gy = 0;
+          ++gz;
+        }
+      }
+      update(cheb_halo_ax<K, T>(aq.v[j], gx, gy, gz, halo, bg, dv, hs), bq.v[j], iq.v[j], dq.v[j], xq.v[j], dn.v[j],
+             xn.v[j]);
+      x8.v[j] = double(xn.v[j]);
+    }
+    store_quad(d, i0, dn);
+    store_quad(x, i0, xn);
+    if (x64) store_quad(x64, i0, x8);
+  }
+  if (blockIdx.x == 0)
+    for (uint32_t i = 4 * nq + threadIdx.x; i < n; i += kBlock) {
+      const uint32_t r = dv.n1.div(i), gz = dv.n1.div(r);
+      const int gx = int(i - r * uint32_t(N1)), gy = int(r - gz * uint32_t(N1));
+      T dn, xn;
+      update(cheb_halo_ax<K, T>(ax[i], gx, gy, int(gz), halo, bg, dv, hs), b[i], dinv[i], d[i], x[i], dn, xn);
+      d[i] = dn;
+      x[i] = xn;
+      if (x64) x64[i] = double(xn);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1171,8 +1235,14 @@ static hipError_t cg_cheb_halo_k(const Context &c, const Level &L, const T *b, c
   if (L.ndofs >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit DoF index space
   const DofDiv dv{FastDiv(uint32_t(L.N1)), FastDiv(uint32_t(bg.sx * K)), FastDiv(uint32_t(bg.my)),
                   FastDiv(uint32_t(bg.mz))};
-  cheb_halo_kernel<K, T><<<grid_for(L.ndofs, 8192), kBlock, 0, s>>>(ax, (const T *)L.halo, b, dinv, d, x, x64, bg,
-                                                                    dv, T(c1), T(c2));
+  // four DoFs per lane where the grid stays full (8192 work-groups); on smaller levels, whose
+  // kernels are latency-bound, one DoF per lane spreads the halo additions over more lanes
+  if (L.ndofs >= int64_t(4) * 8192 * kBlock && aligned16(ax, b, dinv, d, x, x64))
+    cheb_halo_quad_kernel<K, T><<<grid_for(L.ndofs / 4, 8192), kBlock, 0, s>>>(ax, (const T *)L.halo, b, dinv, d, x,
+                                                                               x64, bg, dv, T(c1), T(c2));
+  else
+    cheb_halo_kernel<K, T><<<grid_for(L.ndofs, 8192), kBlock, 0, s>>>(ax, (const T *)L.halo, b, dinv, d, x, x64, bg,
+                                                                      dv, T(c1), T(c2));
   return hipGetLastError();
 }
 
