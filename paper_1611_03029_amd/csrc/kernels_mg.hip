@@ -208,11 +208,23 @@ prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, int d
   const int N1c = K * Ncc + 1, N1f = 2 * K * Ncc + 1;
   const int cxn = K * w.nc + 1;   // coarse points of the row along x (the tiles hold CX)
   // (index decompositions use the compile-time extents; entries past the row stay unused)
-  for (int i = threadIdx.x; i < n * n * CX; i += kBlock) {
+  constexpr int NC = n * n * CX, IC = (NC + kBlock - 1) / kBlock;
+  TC cv[IC];
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {   // all coarse loads first; entries past the row read a valid address
+    const int i = min(int(threadIdx.x) + it * kBlock, NC - 1);
+    const int X = i % CX, bl = i / CX, b = bl % n, l = bl / n;
+    const int gx = min(K * w.cx0 + X, N1c - 1), gy = w.cy * K + b, gz = w.cz * K + l;
+    cv[it] = xc[gx + int64_t(N1c) * (gy + int64_t(N1c) * gz)];
+  }
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    const int i = int(threadIdx.x) + it * kBlock;
+    if (i >= NC) break;
     const int X = i % CX, bl = i / CX, b = bl % n, l = bl / n;
     const int gx = K * w.cx0 + X, gy = w.cy * K + b, gz = w.cz * K + l;
     const bool bnd = X >= cxn || dirichlet_dof(gx, gy, gz, N1c, dmask);
-    b0[i] = bnd ? TF(0) : TF(xc[gx + int64_t(N1c) * (gy + int64_t(N1c) * gz)]);
+    b0[i] = bnd ? TF(0) : TF(cv[it]);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < m * n * CX; i += kBlock) {   // z
@@ -270,17 +282,33 @@ restrict_cell_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TF *
   // weight 1/2 per direction in which the fine node lies on a face shared by two coarse cells
   auto shared_half = [&](int f) { return f % (2 * K) == 0 && f > 0 && f < N1f - 1; };
   // (index decompositions use the compile-time extents; cells past the row are skipped)
-  for (int i = threadIdx.x; i < FX * m * m; i += kBlock) {
+  // All of a lane's tile loads are issued before the first is used: one round trip to
+  // memory per work-group instead of one per tile entry of the lane.  Entries outside the
+  // row read a valid address and are discarded.
+  constexpr int NT = FX * m * m, IT = (NT + kBlock - 1) / kBlock;
+  TF bv[IT], av[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = min(int(threadIdx.x) + it * kBlock, NT - 1);
+    const int X = i % FX, JL = i / FX, J = JL % m, L = JL / m;
+    const int fx = min(2 * K * w.cx0 + X, N1f - 1), fy = 2 * K * w.cy + J, fz = 2 * K * w.cz + L;
+    const int64_t g = fx + int64_t(N1f) * (fy + int64_t(N1f) * fz);
+    bv[it] = bf[g];
+    av[it] = axf ? axf[g] : TF(0);
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = int(threadIdx.x) + it * kBlock;
+    if (i >= NT) break;
     const int X = i % FX, JL = i / FX, J = JL % m, L = JL / m;
     const int fx = 2 * K * w.cx0 + X, fy = 2 * K * w.cy + J, fz = 2 * K * w.cz + L;
     TF v = 0;
     if (X < fxn && !dirichlet_dof(fx, fy, fz, N1f, dmask)) {
-      const int64_t g = fx + int64_t(N1f) * (fy + int64_t(N1f) * fz);
       TF wgt = 1;
       if (shared_half(fx)) wgt *= TF(0.5);
       if (shared_half(fy)) wgt *= TF(0.5);
       if (shared_half(fz)) wgt *= TF(0.5);
-      v = wgt * (axf ? bf[g] - axf[g] : bf[g]);
+      v = wgt * (axf ? bv[it] - av[it] : bv[it]);
     }
     r[i] = v;
   }

@@ -426,6 +426,19 @@ dg_prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, Tr
   const int64_t cell = blockIdx.x;
   const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
   const int Nf = 2 * Ncc;
+  // fine value i of the children, in the order (sz, sy, sx) of the z phase below
+  auto fine_index = [&](int i) {
+    const int sz = i / (4 * n3), rest = i - sz * 4 * n3, sy = rest / (2 * n3), rest2 = rest - sy * 2 * n3;
+    const int sx = rest2 / n3, r = rest2 - sx * n3;
+    const int64_t fc = (2 * cx + sx) + int64_t(Nf) * ((2 * cy + sy) + int64_t(Nf) * (2 * cz + sz));
+    return fc * n3 + r;
+  };
+  // the lane's fine values are loaded first, so that those loads are in flight during the
+  // three phases instead of each waiting before its own update
+  constexpr int NF = 8 * n3, IF = (NF + kBlock - 1) / kBlock;
+  TF xv[IF];
+#pragma unroll
+  for (int it = 0; it < IF; ++it) xv[it] = xf[fine_index(min(int(threadIdx.x) + it * kBlock, NF - 1))];
   for (int i = threadIdx.x; i < n3; i += kBlock) u[i] = TF(xc[cell * n3 + i]);
   __syncthreads();
   for (int i = threadIdx.x; i < 2 * n3; i += kBlock) {   // x: [sx][c][b][a]
@@ -443,13 +456,15 @@ dg_prolongate_kernel(const TC *__restrict__ xc, TF *__restrict__ xf, int Ncc, Tr
     t2[i] = v;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 8 * n3; i += kBlock) {   // z: fine cell (sx, sy, sz)
+#pragma unroll
+  for (int it = 0; it < IF; ++it) {   // z: fine cell (sx, sy, sz)
+    const int i = int(threadIdx.x) + it * kBlock;
+    if (i >= NF) break;
     const int sz = i / (4 * n3), rest = i - sz * 4 * n3, sy = rest / (2 * n3), rest2 = rest - sy * 2 * n3;
     const int sx = rest2 / n3, r = rest2 - sx * n3, a = r % n, b = (r / n) % n, c = r / n2;
     TF v = 0;
     for (int j = 0; j < n; ++j) v += TF(E[(sz * n + c) * n + j]) * t2[(sy * 2 + sx) * n3 + j * n2 + b * n + a];
-    const int64_t fc = (2 * cx + sx) + int64_t(Nf) * ((2 * cy + sy) + int64_t(Nf) * (2 * cz + sz));
-    xf[fc * n3 + r] += v;
+    xf[fine_index(i)] = xv[it] + v;
   }
 }
 
@@ -466,11 +481,23 @@ dg_restrict_kernel(const TF *__restrict__ bf, const TF *__restrict__ axf, TC *__
   const int64_t cell = blockIdx.x;
   const int cx = int(cell % Ncc), cy = int((cell / Ncc) % Ncc), cz = int(cell / (int64_t(Ncc) * Ncc));
   const int Nf = 2 * Ncc;
-  for (int i = threadIdx.x; i < 8 * n3; i += kBlock) {   // children in order (sz, sy, sx)
+  // children in order (sz, sy, sx); all of a lane's loads are issued before the first is used
+  constexpr int NR = 8 * n3, IR = (NR + kBlock - 1) / kBlock;
+  TF bv[IR], av[IR];
+#pragma unroll
+  for (int it = 0; it < IR; ++it) {
+    const int i = min(int(threadIdx.x) + it * kBlock, NR - 1);
     const int ch = i / n3, r = i - ch * n3, sx = ch & 1, sy = (ch >> 1) & 1, sz = ch >> 2;
     const int64_t fc = (2 * cx + sx) + int64_t(Nf) * ((2 * cy + sy) + int64_t(Nf) * (2 * cz + sz));
     const int64_t g = fc * n3 + r;
-    r8[i] = axf ? bf[g] - axf[g] : bf[g];
+    bv[it] = bf[g];
+    av[it] = axf ? axf[g] : TF(0);
+  }
+#pragma unroll
+  for (int it = 0; it < IR; ++it) {
+    const int i = int(threadIdx.x) + it * kBlock;
+    if (i >= NR) break;
+    r8[i] = axf ? bv[it] - av[it] : bv[it];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 4 * n3; i += kBlock) {   // z: [sy][sx][c'][b][a]
