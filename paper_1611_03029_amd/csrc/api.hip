@@ -514,8 +514,8 @@ int smoother_step(Context &c, int l, double *x64_out, int dt, double c1, double 
 // Chebyshev iteration on level l with interval [lo, hi] and `updates` updates of x.
 // zero_start: x = 0 initially and b is taken from b_in (stored into L.b when b_in != L.b).
 // SIPG with the GLL Jacobi smoother fuses the operator into each update, which writes the
-// new x into the level's other x buffer; the buffers alternate and the result is copied back
-// into L.x after an odd number of such updates.
+// new x into the level's other x buffer; the buffers alternate, and after an odd number of
+// such updates L.x and L.x2 exchange roles.
 int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_start, const void *b_in,
               int b_dtype, double *x64_out, hipStream_t s) {
   Level &L = c.levels[l];
@@ -557,7 +557,9 @@ int chebyshev(Context &c, int l, double lo, double hi, int updates, bool zero_st
     if ((rc = step(done + 1 == updates ? x64_out : nullptr, rho_new * rho, 2.0 * rho_new / delta))) return rc;
     rho = rho_new;
   }
-  if (cur != L.x) HIP_TRY(launch_cast(cur, dt, L.x, dt, N, s));
+  // after an odd number of fused updates the result is in the other buffer: the two buffers
+  // trade roles (x is scratch of the cycle; a captured cycle replays the same sequence)
+  if (cur != L.x) std::swap(L.x, L.x2);
   return MFL_OK;
 }
 
