@@ -744,6 +744,17 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
   const int64_t xl0 = cell * n3 + i1 * n2 + i0 * n;   // the lane's x-line (y = i0, z = i1)
   // Loads are unconditional (see sipg_kernel).
   T v[n];   // the cell's values on the lane's x-line, kept for the final update
+  // In FP32 the lane's own lines of b, D'^{-1} and d, read in the later phases, are loaded
+  // first, so that those loads are in flight during the operator phases (15 more VGPRs, the
+  // same 8 waves per SIMD at k = 4; in FP64 the registers would cost occupancy).
+  constexpr bool PRE = sizeof(T) == 4;
+  T bq[n], dpq[n], dq[n];
+  if constexpr (PRE) {
+    load_xline<n>(b + xl0, bq);
+#pragma unroll
+    for (int l = 0; l < n; ++l) dpq[l] = dpinv[cell * n3 + l * n2 + p];
+    load_xline<n>(d + xl0, dq);
+  }
 
   // operator, phase z
   if (inblk) {
@@ -801,7 +812,12 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
     } else {
       load_xline<n>(pr, ur);
     }
-    load_xline<n>(b + xl0, w);
+    if constexpr (PRE) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) w[a] = bq[a];
+    } else {
+      load_xline<n>(b + xl0, w);
+    }
 #pragma unroll
     for (int a = 0; a < n; ++a) v[a] = Uc[o + a];
     sipg_line<n, T>(tb, v, ul, hasL, ur, hasR, inv_h, sigma, dmask, scale, out);
@@ -830,7 +846,7 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       w[l] = Uc[l * n2 + p];
-      dp[l] = dpinv[cell * n3 + l * n2 + p];
+      dp[l] = PRE ? dpq[l] : dpinv[cell * n3 + l * n2 + p];
     }
     eo_apply_t<n, 1>(eo.S, w, r);
 #pragma unroll
@@ -856,7 +872,12 @@ sipg_cheb_kernel(const T *__restrict__ src, const T *__restrict__ b, const T *__
     T w[n], cw[n], dn[n], xn[n];
 #pragma unroll
     for (int a = 0; a < n; ++a) w[a] = Uc[i1 * n2 + i0 * n + a];
-    load_xline<n>(d + xl0, dn);
+    if constexpr (PRE) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) dn[a] = dq[a];
+    } else {
+      load_xline<n>(d + xl0, dn);
+    }
     eo_apply<n, 1>(eo.S, w, cw);
 #pragma unroll
     for (int a = 0; a < n; ++a) {
