@@ -744,7 +744,7 @@ def run_reduction(name, dirs):
         summarize_stats(dirs[0], "GMG-PCG solves of the sine problem, CG Q4 on 64^3 Cartesian cells, "
                         "FP64 and FP32 V-cycles, two solves each", cmd, out, top=40)
     elif name == "sipg_sq":
-        groups = [("sipg_kernel<3, double>", "SIPG Q3, FP64"), ("sipg_kernel<5, double>", "SIPG Q5, FP64")]
+        groups = [("sipg_kernel<3, double, false>", "SIPG Q3, FP64"), ("sipg_kernel<5, double, false>", "SIPG Q5, FP64")]
         summarize_sq(dirs[0], groups, "SIPG operator kernel, Q3 and Q5 on 32^3 and 64^3 cells", cmd, out)
         for i, d in enumerate(dirs[1:]):
             summarize_sq(d, groups, "SIPG operator kernel, Q3 and Q5 on 32^3 and 64^3 cells", cmd,
@@ -756,7 +756,7 @@ def run_reduction(name, dirs):
         for k, nc, n in ((3, 32, 32 ** 3 * 64), (3, 64, 64 ** 3 * 64), (5, 32, 32 ** 3 * 216), (5, 64, 64 ** 3 * 216)):
             cpb = (256 // 64) * (64 // (k + 1) ** 2) if k <= 3 else 256 // (k + 1) ** 2
             grid = 8 * (((nc // 2) * (nc // 4) * nc + cpb - 1) // cpb) * 256
-            kern["Q%d_%d^3" % (k, nc)] = {"match": "sipg_kernel<%d, double>" % k, "grid": grid,
+            kern["Q%d_%d^3" % (k, nc)] = {"match": "sipg_kernel<%d, double, false>" % k, "grid": grid,
                                           "algorithmic_bytes": 16 * n}
         reduce_traffic(dirs[0], dirs[1], 8 * 64 ** 3 * 216, kern, None,
                        "SIPG applies, Q3 and Q5 on 32^3 and 64^3 Cartesian cells, FP64 (16 B/DoF algorithmic)",

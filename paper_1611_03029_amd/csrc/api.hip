@@ -188,7 +188,12 @@ int64_t layout(Context &c, char *base) {
       c.q = b.take<double>(N);
     }
   }
-  c.partials = b.take<double>(kReduceBlocks);
+  // reduction partials: the vector kernels' fixed count, or the SIPG operator's work-groups
+  // when the outer CG takes p . A p from the operator kernel
+  const int64_t np = p.disc == MFL_DISC_SIPG && p.build_mg
+                         ? std::max<int64_t>(kReduceBlocks, sipg_apply_blocks(p.degree, p.cells_per_dim))
+                         : kReduceBlocks;
+  c.partials = b.take<double>(np);
   c.scalars = b.take<double>(kNumScalars);
   c.flags = b.take<int>(kNumFlags);
   return b.off;
@@ -655,9 +660,16 @@ int pcg(Context &c, const double *b, double *x, double rtol, int maxit, int *ite
   HIP_TRY(hipMemcpyAsync(c.pv, c.z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
   double rel = 1.0;
   for (int it = 1; it <= maxit; ++it) {
-    if ((rc = apply_level(c, int(c.levels.size()) - 1, MFL_F64, c.pv, c.q, s))) return rc;
-    HIP_TRY(launch_dot_partial(c.pv, c.q, N, c.partials, s));
-    HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s));
+    if (c.p.disc == MFL_DISC_SIPG) {
+      // q = A p with p . q from the operator kernel's work-group partials
+      int np = 0;
+      HIP_TRY(launch_sipg_apply_dot(c, F, c.pv, c.q, c.partials, &np, s));
+      HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s, np));
+    } else {
+      if ((rc = apply_level(c, int(c.levels.size()) - 1, MFL_F64, c.pv, c.q, s))) return rc;
+      HIP_TRY(launch_dot_partial(c.pv, c.q, N, c.partials, s));
+      HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s));
+    }
     HIP_TRY(launch_pcg_update_xr(x, c.r, c.pv, c.q, c.scalars, N, c.partials, s));
     HIP_TRY(launch_finalize(c.partials, c.scalars, kRR, kFinSum, s));
     if ((rc = read_scalars(c, s))) return rc;

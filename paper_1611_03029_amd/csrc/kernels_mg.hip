@@ -397,10 +397,10 @@ dot_partial_kernel(const double *__restrict__ a, const double *__restrict__ b, i
 }
 
 __global__ void __launch_bounds__(kBlock)
-finalize_kernel(const double *__restrict__ partials, double *__restrict__ sc, int which, int op) {
+finalize_kernel(const double *__restrict__ partials, double *__restrict__ sc, int which, int op, int np) {
   __shared__ double red[kBlock];
   double s = 0;
-  for (int i = threadIdx.x; i < kReduceBlocks; i += kBlock) s += partials[i];
+  for (int i = threadIdx.x; i < np; i += kBlock) s += partials[i];
   s = block_sum(s, red);
   if (threadIdx.x == 0) {
     if (op == kFinSum) {
@@ -645,8 +645,9 @@ hipError_t launch_dot_partial(const double *a, const double *b, int64_t n, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, double *scalars, int which, int op, hipStream_t s) {
-  finalize_kernel<<<1, kBlock, 0, s>>>(partials, scalars, which, op);
+hipError_t launch_finalize(const double *partials, double *scalars, int which, int op, hipStream_t s,
+                           int n_partials) {
+  finalize_kernel<<<1, kBlock, 0, s>>>(partials, scalars, which, op, n_partials);
   return hipGetLastError();
 }
 

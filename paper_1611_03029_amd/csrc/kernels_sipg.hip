@@ -269,9 +269,13 @@ inline bool xline_aligned(std::initializer_list<const void *> ptrs) {
   return true;
 }
 
-template <int K, typename T>
+// DOT: also the work-group's partial sum of src . dst over its cells, written to
+// partials[blockIdx.x] (the conjugate-gradient product p . A p without a pass of its own; a
+// cell's A p is complete inside the kernel).
+template <int K, typename T, bool DOT = false>
 __global__ void __launch_bounds__(kBlock)
-sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma, int dmask) {
+sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma, int dmask,
+            double *__restrict__ partials = nullptr) {
   constexpr int n = K + 1, n2 = n * n, n3 = n2 * n, CPB = DGLanes<K>::cpb;
   constexpr int PS = DGLds<K>::PS, CS = DGLds<K>::CS;
   constexpr bool WL = DGLanes<K>::wave;
@@ -330,6 +334,7 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
   }
   cell_sync<WL>();
   // phase x: lanes own x-lines (y = i0, z = i1); the sum of the three directions is stored
+  double pq = 0;   // DOT: the lane's x-line of src . dst
   if (inblk) {
     T u[n], ul[n], ur[n], out[n];
     const bool hasL = cx > 0, hasR = cx < Nc - 1;
@@ -357,7 +362,16 @@ sipg_kernel(const T *__restrict__ src, T *__restrict__ dst, int Nc, T h, T sigma
 #pragma unroll
       for (int a = 0; a < n; ++a) out[a] += Rc[ol + a];
       store_xline<n, VX>(dst + cell * n3 + o, out);
+      if constexpr (DOT) {
+#pragma unroll
+        for (int a = 0; a < n; ++a) pq += double(u[a]) * double(out[a]);
+      }
     }
+  }
+  if constexpr (DOT) {
+    __shared__ double red[kBlock];
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = pq;
   }
 }
 
@@ -367,7 +381,20 @@ hipError_t sipg_k(const Context &c, const Level &L, const T *src, T *dst, hipStr
   const int grid = 8 * ColumnOrder::blocks_per_xcd(L.Nc, CPB);
   const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
   if (!xline_aligned<K>({src, dst})) return hipErrorInvalidValue;
-  launch_timed(sipg_kernel<K, T>, grid, kBlock, s, ev, src, dst, L.Nc, T(L.h), T(sigma), dirichlet_mask(c.p));
+  launch_timed(sipg_kernel<K, T>, grid, kBlock, s, ev, src, dst, L.Nc, T(L.h), T(sigma), dirichlet_mask(c.p),
+               static_cast<double *>(nullptr));
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t sipg_dot_k(const Context &c, const Level &L, const double *src, double *dst, double *partials, int *n,
+                      hipStream_t s) {
+  constexpr int CPB = DGLanes<K>::cpb;
+  const int grid = 8 * ColumnOrder::blocks_per_xcd(L.Nc, CPB);
+  const double sigma = c.p.penalty_factor * (K + 1) * (K + 1) / L.h;
+  if (!xline_aligned<K>({src, dst})) return hipErrorInvalidValue;
+  sipg_kernel<K, double, true><<<grid, kBlock, 0, s>>>(src, dst, L.Nc, L.h, sigma, dirichlet_mask(c.p), partials);
+  *n = grid;
   return hipGetLastError();
 }
 
@@ -912,6 +939,21 @@ hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const 
 #undef CASE
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_sipg_apply_dot(const Context &c, const Level &L, const double *src, double *dst,
+                                 double *partials, int *n, hipStream_t s) {
+#define CASE(K) return sipg_dot_k<K>(c, L, src, dst, partials, n, s)
+  MFL_DISPATCH_K(c.k, CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+int sipg_apply_blocks(int k, int Nc) {
+#define CASE(K) return 8 * ColumnOrder::blocks_per_xcd(Nc, DGLanes<K>::cpb)
+  MFL_DISPATCH_K(k, CASE)
+#undef CASE
+  return 0;
 }
 
 hipError_t launch_sipg_diagonal(const Context &c, const Level &L, hipStream_t s) {

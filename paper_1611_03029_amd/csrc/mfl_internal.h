@@ -197,6 +197,11 @@ hipError_t launch_lift(const Context &c, const Level &L, double *b, const double
                        hipStream_t s);
 hipError_t launch_sipg_apply(const Context &c, const Level &L, int dtype, const void *src, void *dst,
                              hipStream_t s, const LaunchEvents *ev = nullptr);
+// FP64 SIPG apply dst = A src that also writes the per-work-group partial sums of src . dst
+// (in a fixed order) to partials[0 .. sipg_apply_blocks(k, Nc)); returns that count in *n.
+hipError_t launch_sipg_apply_dot(const Context &c, const Level &L, const double *src, double *dst,
+                                 double *partials, int *n, hipStream_t s);
+int sipg_apply_blocks(int k, int Nc);
 // SIPG: matrix diagonal (FP64, then inverse and FP32 copies), embedding transfers between
 // level `coarse` and the next finer one, and the right-hand side of the three-Gaussian example
 hipError_t launch_sipg_diagonal(const Context &c, const Level &L, hipStream_t s);
@@ -251,7 +256,7 @@ hipError_t launch_restrict_residual(const Context &c, const Level &coarse, const
 hipError_t launch_dot_partial(const double *a, const double *b, int64_t n, double *partials,
                               hipStream_t s);
 hipError_t launch_finalize(const double *partials, double *scalars, int which, int op,
-                           hipStream_t s);
+                           hipStream_t s, int n_partials = kReduceBlocks);
 hipError_t launch_pcg_update_xr(double *x, double *r, const double *p, const double *q,
                                 const double *scalars, int64_t n, double *partials, hipStream_t s);
 hipError_t launch_pcg_update_p(double *p, const double *z, const double *scalars, int64_t n,
