@@ -81,7 +81,7 @@ constexpr int kTallMinBricks = MFL_TALL_MIN_BRICKS;
 // one after another, so on a level with few default bricks (fewer than kShortMaxBricks
 // work-groups on 256 compute units) the chip is mostly idle and the time is the length of
 // that chain; one-chunk bricks give the level more, shorter work-groups (continuous
-// Cartesian levels; degrees whose default brick has several chunks).
+// levels, Cartesian and curved; degrees whose default brick has several chunks).
 template <int K>
 struct ShortShape : Brick<K> {
   static constexpr int chunks = 1, ny = 1, nz = 1;
@@ -1110,14 +1110,14 @@ template <int K>
 constexpr bool kHasShort = Brick<K>::chunks > 1;
 
 // The brick shape of a level: the tall shape when it exists and still gives the mesh
-// kTallMinBricks work-groups; one-chunk bricks on continuous Cartesian levels with fewer
-// than kShortMaxBricks default bricks; Brick<K> otherwise.
+// kTallMinBricks work-groups; one-chunk bricks on levels with fewer than kShortMaxBricks
+// default bricks; Brick<K> otherwise.
 template <int K, typename T, bool CURVED>
 int level_shape(int Nc) {
   if constexpr (TallShape<K, T, CURVED>::tall) {
     if (brick_count<K, T, CURVED, kShapeTall>(Nc) >= kTallMinBricks) return kShapeTall;
   }
-  if constexpr (!CURVED && kHasShort<K>) {
+  if constexpr (kHasShort<K>) {
     if (brick_count<K, T, CURVED, kShapeDefault>(Nc) < kShortMaxBricks) return kShapeShort;
   }
   return kShapeDefault;
@@ -1178,13 +1178,23 @@ static hipError_t cg_apply_k(const Context &c, const Level &L, const Tab<kMaxN, 
   (void)tab;
   const T *none = nullptr;
   if (c.p.geometry == MFL_GEOM_CURVED) {
-    const BrickGrid bg = brick_grid<K, T, true, kShapeDefault>(L.Nc, L.N1, dm);
-    if (metric_on_the_fly(c.p))
-      launch_timed(apply_brick_kernel<K, T, true, kShapeDefault, true>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src,
-                   dst, halo, kappa, metric, bg, T(L.h));
-    else
-      launch_timed(apply_brick_kernel<K, T, true, kShapeDefault>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src, dst,
-                   halo, kappa, metric, bg, T(L.h));
+    auto curved = [&](auto shape) {
+      constexpr int S = decltype(shape)::value;
+      const BrickGrid bg = brick_grid<K, T, true, S>(L.Nc, L.N1, dm);
+      if (metric_on_the_fly(c.p))
+        launch_timed(apply_brick_kernel<K, T, true, S, true>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src, dst, halo,
+                     kappa, metric, bg, T(L.h));
+      else
+        launch_timed(apply_brick_kernel<K, T, true, S>, bg.nbx * bg.nby * bg.nbz, kBlock, s, ev, src, dst, halo,
+                     kappa, metric, bg, T(L.h));
+    };
+    if constexpr (kHasShort<K>) {
+      if (level_shape<K, T, true>(L.Nc) == kShapeShort) {
+        curved(std::integral_constant<int, kShapeShort>{});
+        return hipGetLastError();
+      }
+    }
+    curved(std::integral_constant<int, kShapeDefault>{});
   } else {
     const int shape = level_shape<K, T, false>(L.Nc);
     if constexpr (TallShape<K, T, false>::tall) {
