@@ -1257,42 +1257,66 @@ static hipError_t cg_cheb_halo_k(const Context &c, const Level &L, const T *b, c
 }
 
 // ---------------------------------------------------------------------------------------
-// Coarse-grid solve of the multigrid (Sec. 4.1) on a small Cartesian level in one
+// Coarse-grid solve of the multigrid (Sec. 4.1) on a small continuous level in one
 // work-group: all `steps` updates of the Chebyshev iteration from x = 0 over [lo, hi] of the
 // Jacobi-scaled operator (theta = (lo + hi) / 2, delta = (hi - lo) / 2), with x and A x in
 // LDS and b, D^{-1} and d in registers.  Each update applies the operator cell by cell (the
-// Kronecker-sum cell of cart_cell, added into A x with LDS atomics; identity rows on
+// Kronecker-sum cell of cart_cell or the curved cell, added into A x with LDS atomics; identity rows on
 // Dirichlet DoFs), then d = c1 d + c2 D^{-1} (b - A x), x += d.  The coarsest level holds a
 // few hundred to a few thousand DoFs: there the operator and update kernels of every
 // update are bound by launch and memory latency, while here one launch does all updates.
 // The loop count is `steps`, the same in every thread, so every barrier is reached.
-template <int K, int NC>
+// Curved levels (GEOM 1: stored metric, 2: metric formed from the node displacements) take
+// the curved cell in three buffers; there every lane holds one cell for the whole solve
+// (NPASS = 1), so its geometry factors are formed once, before the updates.
+template <int K, int NC, int GEOM>
 struct CoarseShape {
   static constexpr int n = K + 1, n2 = n * n, n3 = n2 * n;
   static constexpr int N1 = K * NC + 1, N = N1 * N1 * N1, NPT = (N + kBlock - 1) / kBlock;
   static constexpr int CELLS = NC * NC * NC, CPP = kBlock / n2, NPASS = (CELLS + CPP - 1) / CPP;
-  static constexpr long lds = long(sizeof(double)) * (2L * N + 2L * CPP * n3);
-  static constexpr bool fits = lds <= 150L * 1024 && NPT <= 32;
+  static constexpr int NBUF = GEOM == 0 ? 2 : 3;
+  static constexpr long lds = long(sizeof(double)) * (2L * N + long(NBUF) * CPP * n3);
+  static constexpr bool fits = lds <= 150L * 1024 && NPT <= 32 && (GEOM == 0 || NPASS == 1);
 };
 
-template <int K, int NC>
+template <int K, int NC, int GEOM>
 __global__ void __launch_bounds__(kBlock)
 coarse_cheb_kernel(const double *__restrict__ b, const double *__restrict__ dinv,
-                   const double *__restrict__ kappa, double *__restrict__ x_out,
+                   const double *__restrict__ kappa, const double *__restrict__ geo, double *__restrict__ x_out,
                    double *__restrict__ x64, double h, int dmask, int steps, double theta,
                    double delta) {
-  using CS = CoarseShape<K, NC>;
+  using CS = CoarseShape<K, NC, GEOM>;
   constexpr const EOTab<K + 1, double> &eo = ct::Tables<K + 1, double>::eo;
   constexpr int n = CS::n, n2 = CS::n2, n3 = CS::n3, N1 = CS::N1, N = CS::N, NPT = CS::NPT;
   constexpr int CELLS = CS::CELLS, CPP = CS::CPP, NPASS = CS::NPASS;
-  __shared__ double xs[N], ax[N], buf[2][CPP * n3];
+  __shared__ double xs[N], ax[N], buf[CS::NBUF][CPP * n3];
   const int t = threadIdx.x;
   const int slot = t / n2, p = t % n2;
   const bool used = slot < CPP;
   double *A = buf[0] + (used ? slot : 0) * n3, *B = buf[1] + (used ? slot : 0) * n3;
+  double *C = buf[CS::NBUF - 1] + (used ? slot : 0) * n3;
   double bb[NPT], di[NPT], d[NPT];
   bool dir[NPT];
   const double inv_theta = 1.0 / theta;
+  // curved: the metric of the lane's z-line of Gauss points in its (only) cell, with kappa
+  // folded in when it is formed on the fly
+  double g[6][GEOM == 0 ? 1 : n];
+  double kcell = 1.0;
+  if constexpr (GEOM != 0) {
+    const int cell = slot;
+    const bool active = used && cell < CELLS;
+    const int cx = active ? cell % NC : 0, cy = active ? (cell / NC) % NC : 0, cz = active ? cell / (NC * NC) : 0;
+    const CellCtx cc = make_ctx(K, n, p, used, active, cx, cy, cz, N1, dmask);
+    const double kap = active ? kappa[cell] : 0.0;
+    if constexpr (GEOM == 2) {
+      double dz[n];
+      gather_zline_nodes(cc, geo, dz);
+      otf_metric<K, double, false>(cc, dz, A, B, C, eo, h, kap, g);
+    } else {
+      load_metric<n, false>(active, geo + (active ? cell : 0) * (6 * n3), p, g);
+      kcell = kap;
+    }
+  }
   // the thread's DoFs i = t + j kBlock: b, D^{-1}, and the first update from x = 0
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
@@ -1325,9 +1349,14 @@ coarse_cheb_kernel(const double *__restrict__ b, const double *__restrict__ dinv
       double u[n];
 #pragma unroll
       for (int l = 0; l < n; ++l) u[l] = (active && !z_bnd(cc, l)) ? xs[cc.base + cc.plane * l] : 0.0;
-      const double scale = active ? kappa[cell] * h : 0.0;
-      cart_cell<K, double, 0, 0, false>(cc, u, scale, A, B, A, B, eo);
-      // y_e of the lane's x-line (y = i0, z = i1) is in A after the cell's last barrier
+      if constexpr (GEOM == 0) {
+        const double scale = active ? kappa[cell] * h : 0.0;
+        cart_cell<K, double, 0, 0, false>(cc, u, scale, A, B, A, B, eo);
+      } else {
+        curved_cell<K, double, 0, 0, false>(cc, u, g, kcell, A, B, C, eo);
+      }
+      // y_e of the lane's x-line (y = i0, z = i1) is in A after the cell's last barrier (both
+      // cell forms leave it in the layout z n^2 + y n + x)
       if (active) {
         const int g0 = (cz * K + cc.i1) * N1 * N1 + (cy * K + cc.i0) * N1 + cx * K;
 #pragma unroll
@@ -1356,34 +1385,58 @@ coarse_cheb_kernel(const double *__restrict__ b, const double *__restrict__ dinv
   }
 }
 
-template <int K, int NC>
-static hipError_t coarse_cheb_launch(const Context &c, const Level &L, const double *b, double *x,
-                                     double *x64_out, int steps, double theta, double delta, hipStream_t s) {
-  if constexpr (CoarseShape<K, NC>::fits) {
-    coarse_cheb_kernel<K, NC><<<1, kBlock, 0, s>>>(b, L.dinv64, L.kappa64, x, x64_out, L.h, dirichlet_mask(c.p),
-                                                   steps, theta, delta);
+// GEOM of a context: 0 Cartesian, 1 curved with the stored metric, 2 curved with the metric
+// formed on the fly.
+inline int coarse_geom(const Context &c) {
+  if (c.p.geometry != MFL_GEOM_CURVED) return 0;
+  return metric_on_the_fly(c.p) ? 2 : 1;
+}
+
+template <int K, int NC, int GEOM>
+static hipError_t coarse_cheb_launch_g(const Context &c, const Level &L, const double *b, double *x,
+                                       double *x64_out, int steps, double theta, double delta, hipStream_t s) {
+  if constexpr (CoarseShape<K, NC, GEOM>::fits) {
+    const double *geo = GEOM == 2 ? L.disp64 : (GEOM == 1 ? L.metric64 : nullptr);
+    coarse_cheb_kernel<K, NC, GEOM><<<1, kBlock, 0, s>>>(b, L.dinv64, L.kappa64, geo, x, x64_out, L.h,
+                                                         dirichlet_mask(c.p), steps, theta, delta);
     return hipGetLastError();
   }
   return hipErrorNotSupported;
 }
 
+template <int K, int NC>
+static hipError_t coarse_cheb_launch(const Context &c, const Level &L, const double *b, double *x,
+                                     double *x64_out, int steps, double theta, double delta, hipStream_t s) {
+  switch (coarse_geom(c)) {
+    case 0: return coarse_cheb_launch_g<K, NC, 0>(c, L, b, x, x64_out, steps, theta, delta, s);
+    case 1: return coarse_cheb_launch_g<K, NC, 1>(c, L, b, x, x64_out, steps, theta, delta, s);
+    default: return coarse_cheb_launch_g<K, NC, 2>(c, L, b, x, x64_out, steps, theta, delta, s);
+  }
+}
+
+template <int K, int GEOM>
+static bool coarse_cheb_fits_g(int Nc) {
+  return (Nc == 1 && CoarseShape<K, 1, GEOM>::fits) || (Nc == 2 && CoarseShape<K, 2, GEOM>::fits) ||
+         (Nc == 3 && CoarseShape<K, 3, GEOM>::fits);
+}
+
 template <int K>
-static bool coarse_cheb_fits(int Nc) {
-  return (Nc == 1 && CoarseShape<K, 1>::fits) || (Nc == 2 && CoarseShape<K, 2>::fits) ||
-         (Nc == 3 && CoarseShape<K, 3>::fits);
+static bool coarse_cheb_fits(int Nc, int geom) {
+  return geom == 0 ? coarse_cheb_fits_g<K, 0>(Nc) : (geom == 1 ? coarse_cheb_fits_g<K, 1>(Nc) : coarse_cheb_fits_g<K, 2>(Nc));
 }
 
 bool cg_coarse_cheb_supported(const Context &c, const Level &L) {
-  if (c.p.disc != MFL_DISC_CG || c.p.geometry != MFL_GEOM_CARTESIAN || L.mg_f32) return false;
+  if (c.p.disc != MFL_DISC_CG || L.mg_f32) return false;
+  const int geom = coarse_geom(c);
   switch (c.k) {
-    case 1: return coarse_cheb_fits<1>(L.Nc);
-    case 2: return coarse_cheb_fits<2>(L.Nc);
-    case 3: return coarse_cheb_fits<3>(L.Nc);
-    case 4: return coarse_cheb_fits<4>(L.Nc);
-    case 5: return coarse_cheb_fits<5>(L.Nc);
-    case 6: return coarse_cheb_fits<6>(L.Nc);
-    case 7: return coarse_cheb_fits<7>(L.Nc);
-    case 8: return coarse_cheb_fits<8>(L.Nc);
+    case 1: return coarse_cheb_fits<1>(L.Nc, geom);
+    case 2: return coarse_cheb_fits<2>(L.Nc, geom);
+    case 3: return coarse_cheb_fits<3>(L.Nc, geom);
+    case 4: return coarse_cheb_fits<4>(L.Nc, geom);
+    case 5: return coarse_cheb_fits<5>(L.Nc, geom);
+    case 6: return coarse_cheb_fits<6>(L.Nc, geom);
+    case 7: return coarse_cheb_fits<7>(L.Nc, geom);
+    case 8: return coarse_cheb_fits<8>(L.Nc, geom);
     default: return false;
   }
 }
