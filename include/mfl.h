@@ -161,9 +161,11 @@ int mfl_setup(const mfl_params *p, void *workspace, int64_t workspace_bytes,
 
 /* Replace the cellwise kappa (device, n_cells doubles, each finite and > 0) and rebuild
  * everything that depends on it: coarse-level kappa (mean of the 8 children), diagonals,
- * eigenvalue estimates.  Synchronizes `stream`.  Errors: MFL_EINVAL for a NULL handle or
- * array and for a kappa value that is not finite and positive (the handle is then left
- * unchanged), MFL_EHIP. */
+ * eigenvalue estimates.  A kappa equal bit for bit to the handle's current one (for example
+ * the adjoint solve's call with the forward solve's kappa) is recognized on the device and
+ * returns at once, without a rebuild.  Synchronizes `stream`.  Errors: MFL_EINVAL for a
+ * NULL handle or array and for a kappa value that is not finite and positive (the handle is
+ * then left unchanged), MFL_EHIP. */
 int mfl_set_kappa(mfl_handle h, const double *kappa_cells, void *stream);
 
 /* Number of levels (1 without multigrid); level 0 is the coarsest, num_levels-1 the finest. */

@@ -195,6 +195,7 @@ int64_t layout(Context &c, char *base) {
                          : kReduceBlocks;
   c.partials = b.take<double>(np);
   c.scalars = b.take<double>(kNumScalars);
+  if (p.build_mg) c.eig_hist = b.take<double>(3 * std::max(p.eig_iters, 1));
   c.flags = b.take<int>(kNumFlags);
   return b.off;
 }
@@ -304,21 +305,23 @@ int row_mask(const Context &c) { return row_mask(c.p); }
 
 // Jacobi-preconditioned CG on level l from the SplitMix64 start vector (key = cells per
 // direction, Dirichlet entries zero); records the Lanczos tridiagonal from alpha, beta.
+// p.A p, alpha and beta of every iteration are copied to a device history and read once at
+// the end; the recurrence stops at the first iteration whose p.A p is not finite and
+// positive (a zero start residual gives p.A p = 0 at once).
 int lanczos(Context &c, int l, int max_iters, std::vector<double> &diag, std::vector<double> &off,
             hipStream_t s) {
   Level &L = c.levels[l];
   const int64_t N = L.ndofs;
   double *r = c.r, *z = c.z, *p = c.pv, *q = c.q;
+  int rc;
+  max_iters = std::min(max_iters, std::max(c.p.eig_iters, 1));   // the history's length
   HIP_TRY(launch_random_start(r, L, uint64_t(L.Nc), row_mask(c), s));
   HIP_TRY(jacobi_step(c, L, r, z, s));
   HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
   HIP_TRY(launch_finalize(c.partials, c.scalars, kRZ, kFinSum, s));
-  int rc = read_scalars(c, s);
-  if (rc) return rc;
-  const double rz0 = c.host_scalars[kRZ];
-  std::vector<double> alphas, betas;
-  for (int it = 0; it < max_iters && rz0 > 0.0; ++it) {
+  static_assert(kAlpha == kPQ + 1 && kBeta == kPQ + 2, "p.A p, alpha, beta are consecutive scalars");
+  for (int it = 0; it < max_iters; ++it) {
     if ((rc = apply_level(c, l, MFL_F64, p, q, s))) return rc;
     HIP_TRY(launch_dot_partial(p, q, N, c.partials, s));
     HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinAlpha, s));
@@ -328,11 +331,18 @@ int lanczos(Context &c, int l, int max_iters, std::vector<double> &diag, std::ve
     HIP_TRY(launch_dot_partial(r, z, N, c.partials, s));
     HIP_TRY(launch_finalize(c.partials, c.scalars, 0, kFinBeta, s));
     HIP_TRY(launch_pcg_update_p(p, z, c.scalars, N, s));
-    if ((rc = read_scalars(c, s))) return rc;
-    const double pq = c.host_scalars[kPQ];
+    HIP_TRY(hipMemcpyAsync(c.eig_hist + 3 * it, c.scalars + kPQ, 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<double> hist(3 * std::max(max_iters, 0));
+  if (max_iters > 0)
+    HIP_TRY(hipMemcpyAsync(hist.data(), c.eig_hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < max_iters; ++it) {
+    const double pq = hist[3 * it];
     if (!(pq > 0.0) || !std::isfinite(pq)) break;
-    alphas.push_back(c.host_scalars[kAlpha]);
-    betas.push_back(c.host_scalars[kBeta]);
+    alphas.push_back(hist[3 * it + 1]);
+    betas.push_back(hist[3 * it + 2]);
   }
   const int m = int(alphas.size());
   if (m == 0) return fail(MFL_EBREAKDOWN, "eigenvalue estimate on level %d: no CG step possible", l);
@@ -361,7 +371,11 @@ int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax
   const int64_t N = L.ndofs;
   const int64_t unknowns = l == 0 ? coarse_unknowns(c.p) : N;
   const int max_steps = int(std::min<int64_t>(unknowns, 4000));
-  std::vector<double> Q, P, w(N), z(N), alpha, beta;
+  // w, z and the staged p_j in pinned host memory (the coarsest level's length): each step
+  // moves them with direct copies instead of through pageable staging
+  if (!c.host_coarse || N > c.levels.front().ndofs) return fail(MFL_EINVAL, "coarse staging missing");
+  double *w = c.host_coarse, *z = c.host_coarse + N, *pstage = c.host_coarse + 2 * N;
+  std::vector<double> Q, P, alpha, beta;
   auto dot = [N](const double *a, const double *b) {
     double acc = 0.0;
     for (int64_t i = 0; i < N; ++i) acc += a[i] * b[i];
@@ -369,18 +383,18 @@ int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax
   };
   // z = C w on the device
   auto precondition = [&]() -> int {
-    HIP_TRY(hipMemcpyAsync(c.r, w.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.r, w, N * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(jacobi_step(c, L, c.r, c.z, s));
-    HIP_TRY(hipMemcpyAsync(z.data(), c.z, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(z, c.z, N * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MFL_OK;
   };
   HIP_TRY(launch_random_start(c.r, L, uint64_t(L.Nc), row_mask(c), s));
-  HIP_TRY(hipMemcpyAsync(w.data(), c.r, N * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(w, c.r, N * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   int rc = precondition();
   if (rc) return rc;
-  double b0 = dot(w.data(), z.data());
+  double b0 = dot(w, z);
   if (!(b0 > 0.0) || !std::isfinite(b0))
     return fail(MFL_EBREAKDOWN, "coarse eigenvalue range on level %d: start vector has no C-norm", l);
   b0 = std::sqrt(b0);
@@ -398,11 +412,12 @@ int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax
   lmin = lmax = 0.0;
   for (int j = 0; j < max_steps; ++j) {
     const double *qj = Q.data() + int64_t(j) * N, *pj = P.data() + int64_t(j) * N;
-    HIP_TRY(hipMemcpyAsync(c.pv, pj, N * sizeof(double), hipMemcpyHostToDevice, s));
+    std::copy(pj, pj + N, pstage);
+    HIP_TRY(hipMemcpyAsync(c.pv, pstage, N * sizeof(double), hipMemcpyHostToDevice, s));
     if ((rc = apply_level(c, l, MFL_F64, c.pv, c.q, s))) return rc;
-    HIP_TRY(hipMemcpyAsync(w.data(), c.q, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(w, c.q, N * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const double a = dot(pj, w.data());
+    const double a = dot(pj, w);
     for (int64_t i = 0; i < N; ++i) w[i] -= a * qj[i];
     if (j > 0) {
       const double *qp = Q.data() + int64_t(j - 1) * N;
@@ -411,7 +426,7 @@ int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax
     for (int pass = 0; pass < 2; ++pass)
       for (int i = 0; i <= j; ++i) {
         const double *qi = Q.data() + int64_t(i) * N, *pi = P.data() + int64_t(i) * N;
-        const double h = dot(pi, w.data());
+        const double h = dot(pi, w);
         for (int64_t e = 0; e < N; ++e) w[e] -= h * qi[e];
       }
     alpha.push_back(a);
@@ -426,7 +441,7 @@ int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax
       last_max = lmax;
     }
     if ((rc = precondition())) return rc;
-    const double bb = dot(w.data(), z.data());
+    const double bb = dot(w, z);
     if (!(bb > 0.0) || std::sqrt(bb) <= 1e-12 * lmax) break;   // invariant Krylov space
     beta.push_back(std::sqrt(bb));
     push(beta.back());
@@ -799,11 +814,15 @@ int mfl_setup(const mfl_params *p, void *workspace, int64_t workspace_bytes, con
   hipStream_t s = as_stream(stream);
   auto cleanup = [&](int code) {
     if (c->host_scalars) (void)hipHostFree(c->host_scalars);
+    if (c->host_coarse) (void)hipHostFree(c->host_coarse);
     delete c;
     return code;
   };
   if (hipHostMalloc(reinterpret_cast<void **>(&c->host_scalars), kNumScalars * sizeof(double)) != hipSuccess)
     return cleanup(fail(MFL_EHIP, "hipHostMalloc of the scalar mirror failed"));
+  if (p->build_mg && hipHostMalloc(reinterpret_cast<void **>(&c->host_coarse),
+                                   3 * c->levels.front().ndofs * sizeof(double)) != hipSuccess)
+    return cleanup(fail(MFL_EHIP, "hipHostMalloc of the coarse-level staging failed"));
   Level &F = c->levels.back();
   hipError_t e = hipMemsetAsync(c->flags, 0, kNumFlags * sizeof(int), s);
   if (e == hipSuccess) {
@@ -833,8 +852,13 @@ int mfl_set_kappa(mfl_handle h, const double *kappa_cells, void *stream) {
   hipStream_t s = as_stream(stream);
   Level &F = h->levels.back();
   HIP_TRY(hipMemsetAsync(h->flags, 0, kNumFlags * sizeof(int), s));
-  HIP_TRY(launch_check_positive(kappa_cells, F.ncells, h->flags, kFlagKappa, s));
-  if (int rc = setup_flags(*h, s)) return rc;
+  HIP_TRY(launch_check_positive(kappa_cells, F.ncells, h->flags, kFlagKappa, s, F.kappa64, kFlagChanged));
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (f & kFlagKappa) return fail(MFL_EINVAL, "kappa holds a value that is not finite and positive");
+  // the handle's kappa, bit for bit: everything that depends on it is current
+  if (!(f & kFlagChanged)) return MFL_OK;
   HIP_TRY(hipMemcpyAsync(F.kappa64, kappa_cells, F.ncells * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(launch_cast(F.kappa64, MFL_F64, F.kappa32, MFL_F32, F.ncells, s));
   int rc = rebuild_kappa_dependent(*h, s);
@@ -1060,6 +1084,7 @@ int mfl_destroy(mfl_handle h) {
   if (h->vcycle_graph) (void)hipGraphExecDestroy(h->vcycle_graph);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   if (h->host_scalars) (void)hipHostFree(h->host_scalars);
+  if (h->host_coarse) (void)hipHostFree(h->host_coarse);
   for (hipEvent_t e : h->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->prof_stop) (void)hipEventDestroy(e);
   delete h;

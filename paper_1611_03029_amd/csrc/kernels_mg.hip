@@ -29,13 +29,18 @@ __global__ void __launch_bounds__(kBlock) cast_kernel(const A *s, B *d, int64_t 
   GRID_STRIDE(i, n) d[i] = B(s[i]);
 }
 
-__global__ void __launch_bounds__(kBlock) check_positive_kernel(const double *v, int64_t n, int *flag, int bit) {
-  bool bad = false;
+// bit: some value is not finite and positive; with prev, change_bit: some value differs
+// from prev in its bits.
+__global__ void __launch_bounds__(kBlock) check_positive_kernel(const double *v, int64_t n, int *flag, int bit,
+                                                               const double *prev, int change_bit) {
+  bool bad = false, changed = false;
   GRID_STRIDE(i, n) {
     const double x = v[i];
     bad = bad || !(x > 0.0) || !isfinite(x);
+    if (prev) changed = changed || __double_as_longlong(x) != __double_as_longlong(prev[i]);
   }
   if (bad) atomicOr(flag, bit);
+  if (changed) atomicOr(flag, change_bit);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -495,8 +500,9 @@ hipError_t launch_cast(const void *src, int sd, void *dst, int dd, int64_t n, hi
   return hipGetLastError();
 }
 
-hipError_t launch_check_positive(const double *v, int64_t n, int *flag, int bit, hipStream_t s) {
-  check_positive_kernel<<<grid_for(n, 1024), kBlock, 0, s>>>(v, n, flag, bit);
+hipError_t launch_check_positive(const double *v, int64_t n, int *flag, int bit, hipStream_t s, const double *prev,
+                                int change_bit) {
+  check_positive_kernel<<<grid_for(n, 1024), kBlock, 0, s>>>(v, n, flag, bit, prev, change_bit);
   return hipGetLastError();
 }
 

@@ -122,10 +122,12 @@ struct Context {
   TransferTab transfer{};
   // FP64 work vectors of the finest level (PCG and eigenvalue estimates)
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
-  double *partials = nullptr;   // kReduceBlocks doubles
+  double *partials = nullptr;   // reduction partials (at least kReduceBlocks doubles)
   double *scalars = nullptr;    // device scalars (see enum Scalar)
+  double *eig_hist = nullptr;   // multigrid: p.A p, alpha, beta of each eigenvalue-estimate iteration
   int *flags = nullptr;         // device error flags of the setup checks (see enum Flag)
   double *host_scalars = nullptr;   // pinned host mirror
+  double *host_coarse = nullptr;    // multigrid: pinned host staging of three coarsest-level vectors
   // the V-cycle on the work vectors r -> z, captured once as a HIP graph on an internal
   // stream and replayed on the caller's stream (use_graphs); rebuilt when the smoother or
   // coarse-solver parameters change
@@ -154,7 +156,7 @@ enum Scalar { kRZ = 0, kPQ, kAlpha, kBeta, kRR, kBB, kRZnew, kNumScalars = 16 };
 
 // Bits of flags[0], raised by setup kernels: a kappa value that is not finite and positive,
 // a quadrature point of a curved cell with det J <= 0 (or not finite).
-enum Flag { kFlagKappa = 1, kFlagDetJ = 2, kNumFlags = 64 };
+enum Flag { kFlagKappa = 1, kFlagDetJ = 2, kFlagChanged = 4, kNumFlags = 64 };
 
 // ---- host-side tables -------------------------------------------------------
 void gauss_legendre(int n, double *x, double *w);
@@ -185,7 +187,10 @@ hipError_t launch_cg_kappa_grad(const Context &c, const Level &L, const double *
 // parameters ask for it); raises kFlagDetJ in c.flags for a non-positive det J
 hipError_t launch_metric_setup(const Context &c, const Level &L, hipStream_t s);
 // raises `bit` in *flag for every value of v[0..n) that is not finite and positive
-hipError_t launch_check_positive(const double *v, int64_t n, int *flag, int bit, hipStream_t s);
+// flag |= bit if some v[i] is not finite and positive; with prev, flag |= change_bit if some
+// v[i] differs bitwise from prev[i]
+hipError_t launch_check_positive(const double *v, int64_t n, int *flag, int bit, hipStream_t s,
+                                 const double *prev = nullptr, int change_bit = 0);
 hipError_t launch_cg_diagonal(const Context &c, const Level &L, hipStream_t s);
 hipError_t launch_rhs_sine(const Context &c, const Level &L, double *b, hipStream_t s);
 // right-hand side of the three-Gaussian example: forcing and Neumann loads (b = 0 first)

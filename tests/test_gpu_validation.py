@@ -42,6 +42,30 @@ def test_set_kappa_rejects_and_keeps_operator(bad):
     assert (prob.apply(u) - y1).abs().max().item() <= 1e-14 * y1.abs().max().item()
 
 
+def test_set_kappa_with_the_current_kappa_keeps_the_handle():
+    """A kappa equal bit for bit to the handle's is recognized and nothing is rebuilt; any
+    other kappa rebuilds as before (eigenvalue estimates of a fresh setup with it)."""
+    rng = np.random.default_rng(41)
+    k1 = np.exp(rng.normal(0.0, 0.5, 8 ** 3))
+    k2 = k1.copy()
+    k2[100] *= 1.5
+    prob = mfl.Problem(3, 8, build_mg=True, kappa=k1)
+    info = [prob.level_info(l) for l in range(3)]
+    r = torch.tensor(uniform_vector(prob.n_dofs, 701), device="cuda")
+    z0 = prob.vcycle(r).clone()
+    prob.set_kappa(torch.tensor(k1, device="cuda"))
+    assert [prob.level_info(l) for l in range(3)] == info
+    # the brick assembly sums shared DoFs in a varying order: equal to rounding
+    assert (prob.vcycle(r) - z0).abs().max().item() <= 1e-13 * z0.abs().max().item()
+    prob.set_kappa(k2)
+    fresh = mfl.Problem(3, 8, build_mg=True, kappa=k2)
+    for l in range(3):
+        a, b = prob.level_info(l), fresh.level_info(l)
+        for key in ("lambda_max", "coarse_lmin", "coarse_lmax"):
+            assert abs(a[key] - b[key]) <= 1e-12 * max(abs(b[key]), 1e-300)
+    assert prob.level_info(-1)["lambda_max"] != info[-1]["lambda_max"]
+
+
 def test_binding_rejects_bad_outputs():
     prob = mfl.Problem(2, 4, build_mg=True)
     b = prob.rhs_sine()
