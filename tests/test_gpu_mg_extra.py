@@ -96,13 +96,29 @@ def test_coarse_solve_single_level(k, nc, bc):
       to 1e-10 of the largest, and the step counts are equal.
     - The kernel against the oracle's Chebyshev recurrence at the oracle's own interval and
       step count: within the V-cycle bar of 1e-9 (the two intervals differ by rounding)."""
+    check_coarse_solve(k, nc, bc)
+
+
+@pytest.mark.parametrize("mode", [mfl.METRIC_STORED, mfl.METRIC_ON_THE_FLY])
+@pytest.mark.parametrize("k,nc,bc", [(1, 2, "dirichlet"), (2, 2, "mixed"), (3, 2, "dirichlet"), (4, 2, "mixed"),
+                                     (4, 1, "dirichlet"), (5, 1, "mixed"), (5, 2, "dirichlet")])
+def test_coarse_solve_single_level_curved(k, nc, bc, mode):
+    """The same on curved cells (x + 0.1 sin sin sin), with the metric stored and formed on the
+    fly: up to Q4 on 2^3 cells and Q5 on one cell the coarse solve runs in one work-group
+    launch with each lane's metric formed once; Q5 on 2^3 cells keeps the per-update kernels."""
+    check_coarse_solve(k, nc, bc, curve_amp=0.1, metric_mode=mode)
+
+
+def check_coarse_solve(k, nc, bc, curve_amp=0.0, **kw):
     from scipy.sparse.linalg import spsolve
     from seeded_inputs import gaussian_field, uniform_vector
+    print("coarse solve Q%d %d^3 %s curve %g %s" % (k, nc, bc, curve_amp, kw), flush=True)
     kap = np.exp(gaussian_field(nc ** 3, 41 + k, 0.5))
+    geo = dict(geometry=mfl.CURVED, curve_amp=curve_amp) if curve_amp else {}
     prob = mfl.Problem(k, nc, kappa=kap, build_mg=True, min_level_cells=nc,
-                       bc=mfl.MIXED if bc == "mixed" else mfl.DIRICHLET)
+                       bc=mfl.MIXED if bc == "mixed" else mfl.DIRICHLET, **geo, **kw)
     assert prob.num_levels == 1
-    ref = o_mg.Multigrid(nc, k, kappa=kap, min_cells=nc, bc=bc)
+    ref = o_mg.Multigrid(nc, k, kappa=kap, curve_amp=curve_amp, min_cells=nc, bc=bc)
     lev = ref.levels[0]
     info = prob.level_info(0)
     print("coarse interval Q%d %d^3 %s: lmin %.3e (rel %.1e), lmax %.3e (rel %.1e)" % (
