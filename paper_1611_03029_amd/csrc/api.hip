@@ -360,7 +360,8 @@ int lanczos(Context &c, int l, int max_iters, std::vector<double> &diag, std::ve
 // C (the recurrence behind preconditioned CG): q_1 = r / |r|_C from the SplitMix64 start
 // vector, then w = A p_j - alpha_j q_j - beta_{j-1} q_{j-1} with p_j = C q_j, orthogonalized
 // twice against the whole basis, q_{j+1} = w / beta_j with beta_j = (w^T C w)^{1/2}.  The
-// basis vectors live on the host; the products with A and C run on the device.  Full
+// basis vectors live on the host; the products with A run on the device, the point Jacobi
+// step C on the host (SIPG's GLL-basis Jacobi on the device).  Full
 // reorthogonalization keeps the tridiagonal's extreme eigenvalues from stalling below the
 // operator's when the start vector is nearly deflated (a clustered spectrum), which plain
 // CG-Lanczos run until its residual vanishes does not.  Stops when the Krylov space is
@@ -381,8 +382,18 @@ int coarse_interval(Context &c, int l, hipStream_t s, double &lmin, double &lmax
     for (int64_t i = 0; i < N; ++i) acc += a[i] * b[i];
     return acc;
   };
-  // z = C w on the device
+  // z = C w: the point Jacobi step on the host from a copy of D^{-1} (the product of
+  // jacobi_kernel), the GLL-basis Jacobi of SIPG on the device
+  std::vector<double> dinv;
+  if (!gll_jacobi(c)) {
+    dinv.resize(N);
+    HIP_TRY(hipMemcpyAsync(dinv.data(), L.dinv64, N * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   auto precondition = [&]() -> int {
+    if (!dinv.empty()) {
+      for (int64_t i = 0; i < N; ++i) z[i] = dinv[i] * w[i];
+      return MFL_OK;
+    }
     HIP_TRY(hipMemcpyAsync(c.r, w, N * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(jacobi_step(c, L, c.r, c.z, s));
     HIP_TRY(hipMemcpyAsync(z, c.z, N * sizeof(double), hipMemcpyDeviceToHost, s));
