@@ -136,7 +136,7 @@ def time_applies(prob, src, dst, steps, warmup):
     return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches
 
 
-def repetitions(prob, src, dst, reps=20, per_rep=10):
+def repetitions(prob, src, dst, reps=20, per_rep=100):
     """Apply timed in `reps` repetitions of `per_rep` back-to-back applications with events
     on the stream the library launches on (torch's current stream); ms per application."""
     import torch
